@@ -1,0 +1,151 @@
+"""Pins of the oracle's initial state, observables and digest, and of the
+paper's printed examples (CPU only)."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from tests.geometry import hash_np
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_paper_examples_fixture():
+    # Byte layout and forcing pattern printed in arXiv:1208.2428, Sec. 2 / Fig. 1.
+    n = 0
+    with open(os.path.join(GOLDEN, "paper_examples.txt")) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            parts = line.split()
+            if parts[0] == "byte":
+                v = int(parts[1], 2)
+                chans = [] if parts[3] == "-" else [int(c) for c in parts[3].split(",")]
+                assert [c for c in range(7) if (v >> c) & 1] == chans
+                assert (v >> 7) & 1 == int(parts[5])
+                # the oracle's observables read the same layout
+                g = oracle.observe_global(np.full((2, 64), v, dtype=np.uint8))
+                assert g["channels"] == [128 if c in chans else 0 for c in range(7)]
+                assert g["solid"] == 128 * int(parts[5])
+            elif parts[0] == "force":
+                before, after = int(parts[1], 2), int(parts[3], 2)
+                check_forcing_example(before, after)
+            n += 1
+    assert n == 5
+
+
+def check_forcing_example(before, after):
+    # Put `before` on a node whose coin is up at step t, with every particle of
+    # it arriving there by streaming, and a torus large enough that nothing
+    # else interacts.  The rest bit does not move.  Pick a state that does not
+    # scatter (the examples are chosen that way: a lone W-mover, or a W-mover
+    # with rest and SW particles, which is not a colliding configuration).
+    seed, f = 41, 1.0 / 1024
+    W, H = 128, 8
+    key_force = oracle.hash64(seed, oracle.TAG_FORCE)
+    thr = math.floor(f * 2**38)
+    for t in range(1000):
+        coins = []
+        for y in range(H):
+            for w in range(W // 64):
+                h = int(hash_np(np.uint64(key_force), np.uint64((t << 40) + (y << 20) + w)))
+                if (h & 0xFFFFFFFF) < thr:
+                    coins.append((y, 64 * w + (h >> 58)))
+        if len(coins) == 1:
+            break
+    (cy, cx), = coins
+    table = oracle.collision_table(0), oracle.collision_table(1)
+    assert table[0][before & 0x7F] == before & 0x7F == table[1][before & 0x7F]
+    # build the pre-streaming state: particle i at the node it comes from
+    s = np.zeros((H, W), dtype=np.uint8)
+    from tests.geometry import node_at, position, velocity
+    px, py = position(cx, cy)
+    for i in range(6):
+        if (before >> i) & 1:
+            vx, vy = velocity(i)
+            sx, sy = node_at(px - vx, py - vy, W, H)
+            s[sy, sx] |= 1 << i
+    s[cy, cx] |= before & 0x40
+    out, swaps = oracle.step(s, t, seed, force_rate=f)
+    assert swaps == 1
+    assert out[cy, cx] == after
+
+
+@pytest.mark.parametrize("fill", [0.0, 0.2, 1.0])
+def test_init_definition(fill):
+    W, H, seed = 128, 6, 99
+    mask = np.zeros((H, W), dtype=np.uint8)
+    mask[2, 5:9] = 1
+    s = oracle.init(W, H, seed, fill, mask=mask, walls=True)
+    key = oracle.hash64(seed, oracle.TAG_INIT)
+    thr = math.floor(fill * 2**32)
+    ys, xs = np.mgrid[0:H, 0:W].astype(np.uint64)
+    expect = np.zeros((H, W), dtype=np.uint8)
+    for c in range(7):
+        h = hash_np(np.uint64(key), (np.uint64(c) << np.uint64(40)) + (ys << np.uint64(20)) + xs)
+        expect |= ((h >> np.uint64(32)) < np.uint64(thr)).astype(np.uint8) << c
+    solid = (mask == 1) | np.isin(np.arange(H), [0, H - 1])[:, None]
+    expect = np.where(solid, 0x80, expect).astype(np.uint8)
+    np.testing.assert_array_equal(s, expect)
+    if fill == 1.0:
+        assert np.all(s[~solid] == 0x7F)
+
+
+def test_init_rate():
+    s = oracle.init(512, 256, seed=3, fill=0.3)
+    frac = [(s >> c & 1).mean() for c in range(7)]
+    sd = math.sqrt(0.3 * 0.7 / s.size)
+    assert all(abs(f - 0.3) < 5 * sd for f in frac)
+
+
+def test_global_and_block_observables():
+    rng = np.random.default_rng(0)
+    W, H = 192, 40
+    s = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    g = oracle.observe_global(s)
+    n = np.stack([(s >> c) & 1 for c in range(7)]).astype(np.int64)
+    # momenta from the unit vectors c_i = angle (i-2)*60 deg, in units (1/2, sqrt(3)/2)
+    ang = np.radians((np.arange(6) - 2) * 60.0)
+    cx = np.round(np.cos(ang) * 2).astype(np.int64)
+    cy = np.round(np.sin(ang) / (math.sqrt(3) / 2)).astype(np.int64)
+    assert g["mass"] == int(n.sum())
+    assert g["px"] == int((n[:6].sum(axis=(1, 2)) * cx).sum())
+    assert g["py"] == int((n[:6].sum(axis=(1, 2)) * cy).sum())
+    assert g["channels"] == [int(v) for v in n.sum(axis=(1, 2))]
+    assert g["solid"] == int((s >> 7).sum())
+    for b in (1, 4, 16, 64, 7):
+        blk = oracle.observe_blocks(s, b)
+        assert blk.shape == ((H + b - 1) // b, (W + b - 1) // b, 3)
+        # sum of blocks equals global sums (ragged tails included)
+        assert int(blk[..., 0].sum()) == g["mass"]
+        assert int(blk[..., 1].sum()) == g["px"]
+        assert int(blk[..., 2].sum()) == g["py"]
+        # one block by brute force
+        by, bx = (H - 1) // b, 1 % ((W + b - 1) // b)
+        sub = n[:, by * b:(by + 1) * b, bx * b:(bx + 1) * b]
+        assert blk[by, bx, 0] == sub.sum()
+        assert blk[by, bx, 1] == int((sub[:6].sum(axis=(1, 2)) * cx).sum())
+
+
+def test_digest_definition_and_sensitivity():
+    rng = np.random.default_rng(1)
+    W, H = 256, 6
+    s = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    d = oracle.digest(s)
+    expect = np.uint64(0)
+    for c in range(8):
+        plane = ((s >> c) & 1).astype(np.uint8)
+        words = np.packbits(plane, axis=1, bitorder="little").view("<u8")  # (H, W/64)
+        ys, ws = np.mgrid[0:H, 0:W // 64].astype(np.uint64)
+        h = hash_np(words, (np.uint64(c) << np.uint64(40)) + (ys << np.uint64(20)) + ws)
+        with np.errstate(over="ignore"):
+            expect = expect + h.sum(dtype=np.uint64)
+    assert d == int(expect)
+    # every single-bit change moves the digest
+    for (y, x, c) in [(0, 0, 0), (5, 255, 7), (3, 100, 6)]:
+        t = s.copy()
+        t[y, x] ^= 1 << c
+        assert oracle.digest(t) != d
