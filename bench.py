@@ -1,0 +1,163 @@
+"""Benchmark: FHP node updates per second on one MI355X, against the HBM roofline.
+
+Workload: the 16384 x 16384 porous medium (solid disks r = 8..32 covering 5%,
+periodic box, fill 0.3, forcing 5e-4), stepped with the library's temporally
+blocked kernel.  One benchmark step is one FHP time step of the whole lattice
+(motion + collision + bounce-back + forcing, arXiv:1208.2428 Sec. 2); the
+unit is the paper's lattice-site update (Sec. 4).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+PLANE_BITS = 14        # 7 planes read + 7 written per node and HBM pass
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def golden_digest(name: str, t: int):
+    path = os.path.join(ROOT, "tests", "golden", f"digests_{name}.txt")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#"):
+                continue
+            parts = line.split()
+            if int(parts[0]) == t:
+                return int(parts[1], 16)
+    return None
+
+
+def cpu_baseline(wl, mask, seconds: float):
+    """Times the CPU oracle on a bounded sample of the workload: a full-width
+    band of 1024 rows of the same lattice (same mask rows, fill and forcing),
+    stepped until `seconds` have elapsed, on all host cores (capped at 16)."""
+    import oracle
+    threads = oracle.default_threads()
+    rows = min(1024, wl.height)
+    band = mask[:rows] if mask is not None else None
+    state = oracle.init(wl.width, rows, wl.seed, wl.fill, mask=band, walls=wl.walls)
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        state, _ = oracle.step(state, steps, wl.seed, wl.force_rate, threads=threads)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    rate = wl.width * rows * steps / el
+    return {"value": rate, "unit": "node-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{wl.width}x{rows} band (rows 0-{rows - 1}) of {wl.name}, "
+                      f"{steps} steps in {el:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--depth", type=int, default=0, help="temporal-block depth k (0 = default)")
+    ap.add_argument("--workload", default="porous-16384")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1208_2428_amd import Sim
+    from paper_1208_2428_amd import workloads as WL
+
+    wl = WL.WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    log(f"bench: {wl.name} {wl.width}x{wl.height}, building mask")
+    mask = wl.mask()
+    solid_frac = float(mask.mean()) if mask is not None else 0.0
+
+    warm = Sim(**wl.params(), solid=mask, depth=args.depth)
+    depth = warm.depth
+    log(f"bench: warmup {args.warmup} steps at depth {depth}")
+    warm.step(args.warmup)
+    warm.sync()
+    warm.close()
+    del warm
+
+    sim = Sim(**wl.params(), solid=mask, depth=depth)
+    nodes = wl.width * wl.height
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_s = e0.elapsed_time(e1) / 1e3
+    log(f"bench: {args.steps} steps in {wall * 1e3:.2f} ms wall, {ev_s * 1e3:.2f} ms events")
+
+    digest = sim.digest()
+    ref = golden_digest(wl.name, args.steps)
+    parity = None if ref is None else (digest == ref)
+    log(f"bench: digest at t={args.steps}: {digest:016x}, oracle {'n/a' if ref is None else f'{ref:016x}'}")
+
+    # Per-launch duration of the step kernel, with events on the kernel's stream.
+    launches = max(1, min(200, args.steps // depth))
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(launches)]
+    for a, b in evs:
+        a.record(stream)
+        sim.step(depth)
+        b.record(stream)
+    torch.cuda.synchronize()
+    launch_s = sum(a.elapsed_time(b) for a, b in evs) / launches / 1e3
+    bytes_per_launch = PLANE_BITS * nodes / 8  # 14/k bits per node-step, k steps per launch
+    achieved = bytes_per_launch / launch_s / 1e9
+    sim.close()
+
+    value = nodes * args.steps / wall
+    out = {
+        "metric": "FHP node updates/sec at 16384^2 vs HBM roofline",
+        "value": value,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "width": wl.width, "height": wl.height,
+                   "fill": wl.fill, "force_rate": wl.force_rate,
+                   "solid_fraction": round(solid_frac, 5), "depth": depth,
+                   "parity_digest_vs_oracle": parity},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel_us": launch_s * 1e6, "bytes_per_launch": bytes_per_launch},
+    }
+    if not args.no_cpu_baseline:
+        log(f"bench: timing the CPU oracle for ~{args.cpu_seconds:.0f} s")
+        out["cpu_baseline"] = cpu_baseline(wl, mask, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

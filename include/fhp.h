@@ -1,0 +1,159 @@
+/*
+ * fhp.h -- C ABI of the MI355X (gfx950) FHP lattice-gas library.
+ *
+ * The library advances the FHP cellular automaton of Szkoda, Koza & Tykierko,
+ * "Accelerating cellular automata simulations using AVX and CUDA"
+ * (arXiv:1208.2428):
+ *   - Sec. 2: seven boolean channels per node of a triangular lattice (six
+ *     velocities c_0..c_5 and a rest particle) plus a boundary flag, one byte
+ *     per node (Fig. 1); a time step is motion to the six nearest neighbours
+ *     followed by scattering that conserves mass and momentum; boundary nodes
+ *     reflect particles; the triangular lattice is stored as a rectangular
+ *     array with every second row shifted by half a lattice constant (Fig. 3);
+ *     walls on top and bottom, periodic in x (Fig. 4); a constant horizontal
+ *     force realised by exchanging bits 2 and 5 with some probability;
+ *   - Sec. 4: throughput is counted in lattice-site updates per second.
+ *
+ * Readings of points the paper leaves open (they define the results bit for
+ * bit, and the CPU oracle used by the tests implements the same readings
+ * independently):
+ *   - numbering: odd rows are shifted by +1/2; c_i points at (i-2)*60 degrees
+ *     (c_2 = E, c_3 = NE, c_4 = NW, c_5 = W, c_0 = SW, c_1 = SE);
+ *   - collisions: FHP-II (head-on pairs turn by +-60 degrees according to a
+ *     chirality bit, rest particle as spectator; the symmetric triples swap
+ *     without rest particle; one particle plus rest <-> the two particles at
+ *     +-60 degrees from it);
+ *   - the step is: stream (pull from the neighbours), then collide (fluid) or
+ *     bounce back c_i -> c_{i+3} (solid, rest particle kept), then forcing;
+ *   - H(key, n) = SplitMix64 output n+1 from state key (Steele, Lea & Flood
+ *     2014); key_tag = H(seed, tag) with tags INIT=1, CHIR=2, FORCE=3;
+ *   - chirality of node (x, y) at step t (t = steps already done) is bit
+ *     x mod 64 of H(key_chir, t*2^40 + y*2^20 + floor(x/64));
+ *   - forcing coin: with h = H(key_force, t*2^40 + y*2^20 + floor(x/64)) the
+ *     coin is up iff (h mod 2^32) < floor(f*2^38) and h>>58 == x mod 64; on a
+ *     fluid node whose post-collision state has bit 5 set and bit 2 clear,
+ *     bits 5 and 2 are exchanged;
+ *   - initial state: fluid node bit c (0..6) is set iff
+ *     (H(key_init, c*2^40 + y*2^20 + x) >> 32) < floor(fill*2^32); solid nodes
+ *     start empty.
+ * The lattice is a torus in both directions; FHP_WALLS_CHANNEL makes rows 0 and
+ * H-1 solid.
+ *
+ * Device layout: seven bit-planes of uint64 words per buffer (bit b of word w
+ * of row y is node x = 64w + b), two buffers (ping-pong), one solid plane.
+ * Interchange layout (get/set state): the paper's byte per node, row-major
+ * [y][x], bits 0-5 moving, bit 6 rest, bit 7 solid.
+ *
+ * Ownership: the caller owns every host buffer and the device workspace; the
+ * library keeps only the pointers it was given and never frees them.  Calls
+ * return FHP_OK (0) or a negative FHP_E_* code; fhp_last_error() returns a
+ * message for the calling thread's last failure.  A handle is not thread-safe.
+ * Work is enqueued on the handle's HIP stream; asynchronous device faults are
+ * reported as FHP_E_DEVICE by the next call that synchronises.
+ */
+#ifndef FHP_H
+#define FHP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FHP_ABI_VERSION 1u
+#define FHP_MAX_DEPTH 8u /* largest temporal-block depth k of one HBM pass */
+
+enum {
+    FHP_OK = 0,
+    FHP_E_INVAL = -1,  /* bad argument, size or layout */
+    FHP_E_NOMEM = -2,  /* workspace or destination too small */
+    FHP_E_DEVICE = -3, /* HIP runtime or kernel error */
+    FHP_E_STATE = -4,  /* time counter would exceed 2^24 steps */
+    FHP_E_BUSY = -5    /* no room (pool admission) */
+};
+
+enum { FHP_WALLS_NONE = 0, FHP_WALLS_CHANNEL = 1 };
+enum { FHP_CHIR_HASH = 0, FHP_CHIR_ZERO = 1, FHP_CHIR_ONE = 2 };
+
+/* Observable kinds for fhp_observe. */
+enum {
+    /* int64[11]: mass, p_x, p_y (momentum in units (1/2, sqrt(3)/2)),
+     * particle count of channels 0..6, number of solid nodes; summed over all
+     * nodes, solid ones included. */
+    FHP_OBS_GLOBAL = 0,
+    /* int32[ceil(H/b)][ceil(W/b)][3]: (rho, p_x, p_y) summed over b x b blocks
+     * in index space; b must divide 64 or be a multiple of 64. */
+    FHP_OBS_BLOCKS = 1,
+    /* uint64[1]: sum over planes c = 0..7 (7 = solid), rows y and words w of
+     * H(word, c*2^40 + y*2^20 + w) mod 2^64. */
+    FHP_OBS_DIGEST = 2
+};
+
+typedef struct fhp_params {
+    uint32_t abi_version; /* FHP_ABI_VERSION */
+    uint32_t width;       /* W: multiple of 64, < 2^20 */
+    uint32_t height;      /* H: even, >= 2, < 2^20 */
+    uint32_t walls;       /* FHP_WALLS_* */
+    uint32_t chirality;   /* FHP_CHIR_*; ZERO and ONE are test modes */
+    uint32_t reserved;    /* must be 0 */
+    uint64_t seed;
+    double fill;          /* per-channel occupancy of fluid nodes at t = 0, in [0, 1] */
+    double force_rate;    /* forcing coin rate f per node and step, in [0, 1/64) */
+    const uint8_t *solid; /* optional host mask, W*H bytes row-major, nonzero = solid;
+                             copied at create; NULL = no obstacles */
+} fhp_params;
+
+typedef struct fhp_sim fhp_sim;
+
+/* Message describing the calling thread's most recent error ("" if none). */
+const char *fhp_last_error(void);
+
+/* Device workspace needed by fhp_create for these parameters. */
+int fhp_workspace_bytes(const fhp_params *p, size_t *bytes);
+
+/* Creates a simulation at t = 0 with the initial state defined above.
+ * dev_ws: device memory of at least fhp_workspace_bytes, 256-byte aligned, owned
+ * by the caller and kept alive until fhp_destroy.  hip_stream: a hipStream_t
+ * (NULL = default stream) on which all work of this handle is enqueued.
+ * Synchronises the stream before returning. */
+int fhp_create(const fhp_params *p, void *dev_ws, size_t ws_bytes, void *hip_stream,
+               fhp_sim **out);
+
+/* Temporal-block depth k (1..FHP_MAX_DEPTH): fhp_step runs k steps per pass over
+ * HBM.  0 selects the library's default for this lattice.  Results do not depend
+ * on k. */
+int fhp_set_depth(fhp_sim *s, uint32_t k);
+int fhp_get_depth(const fhp_sim *s, uint32_t *k);
+
+/* Advances n steps (Sec. 2: motion then scattering, each step).  Asynchronous:
+ * enqueued on the handle's stream.  FHP_E_STATE if t + n would reach 2^24. */
+int fhp_step(fhp_sim *s, uint64_t n);
+
+/* Computes an observable of the current state into host_dst (dst_bytes long)
+ * and synchronises.  block is used by FHP_OBS_BLOCKS only. */
+int fhp_observe(fhp_sim *s, int kind, uint32_t block, void *host_dst, size_t dst_bytes);
+
+/* Copies the current state to host_dst in the byte-per-node layout (W*H bytes,
+ * bit 7 = solid).  Synchronises. */
+int fhp_get_state(fhp_sim *s, uint8_t *host_dst, size_t bytes);
+
+/* Replaces the state by host_src (W*H bytes, byte-per-node layout) and sets the
+ * time counter to t.  Bit 7 becomes the obstacle mask; with FHP_WALLS_CHANNEL
+ * rows 0 and H-1 stay solid whatever bit 7 says.  Particles on solid nodes are
+ * allowed.  Synchronises. */
+int fhp_set_state(fhp_sim *s, const uint8_t *host_src, size_t bytes, uint64_t t);
+
+/* Steps completed so far. */
+int fhp_time(const fhp_sim *s, uint64_t *t);
+
+/* Waits for the handle's work; reports asynchronous device errors. */
+int fhp_sync(fhp_sim *s);
+
+/* Releases the handle (host memory only; the workspace stays the caller's). */
+void fhp_destroy(fhp_sim *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

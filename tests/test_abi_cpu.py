@@ -1,0 +1,83 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+that include/fhp.h declares, and rejects bad parameters before touching the
+device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1208_2428_amd import _binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(fhp_\w+)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.lib_path()):
+        from paper_1208_2428_amd import build
+        build.build()
+    return B.load()
+
+
+def test_exports_every_declared_function(lib):
+    names = declared_functions()
+    assert {"fhp_create", "fhp_step", "fhp_observe"} <= names
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert set(B._SIGNATURES) <= names
+
+
+def test_struct_layout_matches_header():
+    # abi_version .. reserved: 6 x u32, seed u64, fill/force f64, pointer
+    assert ctypes.sizeof(B.Params) == 6 * 4 + 8 + 8 + 8 + 8
+    assert B.Params.seed.offset == 24
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(width=100), B.E_INVAL), (dict(width=0), B.E_INVAL), (dict(width=1 << 20), B.E_INVAL),
+    (dict(height=3), B.E_INVAL), (dict(height=0), B.E_INVAL), (dict(fill=1.5), B.E_INVAL),
+    (dict(fill=float("nan")), B.E_INVAL), (dict(force_rate=1.0 / 64), B.E_INVAL),
+    (dict(force_rate=-1e-9), B.E_INVAL), (dict(chirality=7), B.E_INVAL)])
+def test_bad_params_rejected(lib, kw, code):
+    args = dict(width=128, height=4)
+    args.update(kw)
+    p, _ = B.make_params(**args)
+    n = ctypes.c_size_t()
+    assert lib.fhp_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == code
+    assert lib.fhp_last_error()
+
+
+def test_workspace_size_and_create_argument_checks(lib):
+    p, _ = B.make_params(16384, 16384)
+    n = B.workspace_bytes(p)
+    planes = 16384 * 16384 // 8
+    assert 15 * planes <= n < 15 * planes + 65536
+    h = ctypes.c_void_p()
+    # NULL and misaligned workspaces, and a workspace that is too small, fail
+    # before any device call
+    assert lib.fhp_create(ctypes.byref(p), None, n, None, ctypes.byref(h)) == B.E_INVAL
+    assert lib.fhp_create(ctypes.byref(p), ctypes.c_void_p(8), n, None, ctypes.byref(h)) == B.E_INVAL
+    assert lib.fhp_create(ctypes.byref(p), ctypes.c_void_p(4096), n - 1, None,
+                          ctypes.byref(h)) == B.E_NOMEM
+    p.abi_version = 99
+    assert lib.fhp_workspace_bytes(ctypes.byref(p), ctypes.byref(ctypes.c_size_t())) == B.E_INVAL
+
+
+def test_null_handle_calls_fail_cleanly(lib):
+    assert lib.fhp_step(None, 1) == B.E_INVAL
+    assert lib.fhp_sync(None) == B.E_INVAL
+    assert lib.fhp_set_depth(None, 1) == B.E_INVAL
+    lib.fhp_destroy(None)
