@@ -121,10 +121,14 @@ int fhp_create(const fhp_params *p, void *dev_ws, size_t ws_bytes, void *hip_str
                fhp_sim **out);
 
 /* Temporal-block depth k (1..FHP_MAX_DEPTH): fhp_step runs k steps per pass over
- * HBM.  0 selects the library's default for this lattice.  Results do not depend
- * on k. */
+ * HBM (the last pass of a call may be shorter).  0 selects the library's default
+ * for this lattice.  k > 1 needs width <= 32768.  Results do not depend on k. */
 int fhp_set_depth(fhp_sim *s, uint32_t k);
 int fhp_get_depth(const fhp_sim *s, uint32_t *k);
+
+/* Rows per workgroup band of the blocked kernel (0 = library default).  Each
+ * band also reads K halo rows above and below it.  Results do not depend on it. */
+int fhp_set_band(fhp_sim *s, uint32_t rows);
 
 /* Advances n steps (Sec. 2: motion then scattering, each step).  Asynchronous:
  * enqueued on the handle's stream.  FHP_E_STATE if t + n would reach 2^24. */

@@ -54,6 +54,7 @@ _SIGNATURES = {
                                   ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
     "fhp_set_depth": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     "fhp_get_depth": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
+    "fhp_set_band": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     "fhp_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "fhp_observe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p,
                                    ctypes.c_size_t]),

@@ -75,6 +75,16 @@ Layout layout_for(uint32_t W, uint32_t H) {
     return l;
 }
 
+// Default temporal-block depth: two steps per HBM pass where the blocked
+// kernel applies (full-row workgroups need at most 1024 words per row).
+uint32_t default_depth(uint32_t wd) { return wd <= kMaxBlockedWords ? 2 : 1; }
+
+// Default band height of the blocked kernel.
+uint32_t default_band(uint32_t H, uint32_t K) {
+    (void)K;
+    return H < 32 ? H : 32;
+}
+
 }  // namespace
 
 struct fhp_sim {
@@ -88,7 +98,8 @@ struct fhp_sim {
     uint64_t* aux;
     int cur;
     uint64_t t;
-    uint32_t depth;
+    uint32_t depth;  // temporal-block depth K
+    uint32_t band;   // rows per workgroup of the blocked kernel
     int has_mask;
     hipStream_t st;
 };
@@ -167,7 +178,8 @@ int fhp_create(const fhp_params* p, void* dev_ws, size_t ws_bytes, void* hip_str
     s->aux = s->ws + lay.aux_off;
     s->cur = 0;
     s->t = 0;
-    s->depth = 1;
+    s->depth = default_depth(s->L.wd);
+    s->band = 0;
     s->st = (hipStream_t)hip_stream;
     s->L.W = p->width;
     s->L.H = p->height;
@@ -203,8 +215,17 @@ int fhp_create(const fhp_params* p, void* dev_ws, size_t ws_bytes, void* hip_str
 
 int fhp_set_depth(fhp_sim* s, uint32_t k) {
     if (!s) return fail(FHP_E_INVAL, "sim is NULL");
-    if (k > 1) return fail(FHP_E_INVAL, "depth %u: only k = 1 is available", k);
-    s->depth = k ? k : 1;
+    if (k > FHP_MAX_DEPTH) return fail(FHP_E_INVAL, "depth %u above %u", k, FHP_MAX_DEPTH);
+    if (k > 1 && s->L.wd > kMaxBlockedWords)
+        return fail(FHP_E_INVAL, "depth %u needs width <= %u", k, 64 * kMaxBlockedWords);
+    s->depth = k ? k : default_depth(s->L.wd);
+    return FHP_OK;
+}
+
+int fhp_set_band(fhp_sim* s, uint32_t rows) {
+    if (!s) return fail(FHP_E_INVAL, "sim is NULL");
+    if (rows > s->L.H) return fail(FHP_E_INVAL, "band of %u rows exceeds height %u", rows, s->L.H);
+    s->band = rows;
     return FHP_OK;
 }
 
@@ -220,10 +241,17 @@ int fhp_step(fhp_sim* s, uint64_t n) {
         return fail(FHP_E_STATE, "time %llu + %llu would reach 2^24",
                     (unsigned long long)s->t, (unsigned long long)n);
     const Lattice L = lattice_of(s);
-    for (uint64_t i = 0; i < n; i++) {
-        HIP_TRY(launch_step1(s->buf[s->cur], s->buf[1 - s->cur], L, s->D, s->t, s->st), "step");
+    const uint32_t T = s->band ? s->band : default_band(s->L.H, s->depth);
+    while (n > 0) {
+        uint32_t k = (n >= s->depth) ? s->depth : (uint32_t)n;
+        if (k == 1)
+            HIP_TRY(launch_step1(s->buf[s->cur], s->buf[1 - s->cur], L, s->D, s->t, s->st), "step");
+        else
+            HIP_TRY(launch_stepk(k, s->buf[s->cur], s->buf[1 - s->cur], L, s->D, s->t, T, s->st),
+                    "step");
         s->cur ^= 1;
-        s->t += 1;
+        s->t += k;
+        n -= k;
     }
     return FHP_OK;
 }

@@ -26,7 +26,8 @@ class Sim:
 
     def __init__(self, width: int, height: int, seed: int = 0, fill: float = 0.0,
                  force_rate: float = 0.0, walls: bool = False, chirality: int = B.CHIR_HASH,
-                 solid: np.ndarray | None = None, device=None, stream=None, depth: int = 0):
+                 solid: np.ndarray | None = None, device=None, stream=None, depth: int = 0,
+                 band: int = 0):
         lib = B.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the FHP library needs a ROCm GPU (torch.cuda is unavailable)")
@@ -46,6 +47,8 @@ class Sim:
         self._lib = lib
         if depth:
             self.depth = depth
+        if band:
+            self.set_band(band)
 
     # ---------------------------------------------------------------- control
     def _handle(self):
@@ -65,6 +68,9 @@ class Sim:
     @depth.setter
     def depth(self, k: int) -> None:
         B.check(self._lib.fhp_set_depth(self._handle(), int(k)))
+
+    def set_band(self, rows: int) -> None:
+        B.check(self._lib.fhp_set_band(self._handle(), int(rows)))
 
     @property
     def t(self) -> int:

@@ -1,0 +1,85 @@
+"""GPU vs oracle parity of the temporally blocked step (K steps per HBM pass),
+over depths, band heights, ragged lattice sizes and boundary cases.
+Bit-exact: one correct result exists."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1208_2428_amd import Sim
+from paper_1208_2428_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+THREADS = oracle.default_threads()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def make_state(rng, W, H, case):
+    st = WL.random_states(rng, H, W, p=0.3)
+    if case in ("mask", "mask+force", "solid-particles"):
+        st |= ((rng.random((H, W)) < 0.15).astype(np.uint8) << 7)
+    if case == "solid-particles":
+        st |= WL.random_states(rng, H, W, p=0.5) & 0x7F
+    if "walls" in case:
+        st[0] |= 0x80
+        st[-1] |= 0x80
+    return st
+
+
+@pytest.mark.parametrize("W,H", [(64, 2), (64, 6), (192, 10), (320, 34), (1024, 70), (4096, 40)])
+@pytest.mark.parametrize("K", [2, 3, 4, 8])
+def test_depths_every_pass(W, H, K):
+    say("blocked", W, H, K)
+    rng = np.random.default_rng(W + 7 * H + K)
+    f = 1.0 / 80
+    walls = (W + H) % 2 == 0
+    case = "walls+force" if walls else "mask+force"
+    st = make_state(rng, W, H, case)
+    s = Sim(W, H, seed=31, force_rate=f, walls=walls, depth=K)
+    s.set_state(st, t=5)
+    ref = st.copy()
+    t = 5
+    for n in (K, K, 1, K + 1, 2 * K + 3):
+        s.step(n)
+        ref, _ = oracle.run(ref, t, n, 31, f, threads=THREADS)
+        t += n
+        np.testing.assert_array_equal(s.get_state(), ref, err_msg=f"after step to t={t}")
+    assert s.t == t
+
+
+@pytest.mark.parametrize("band", [1, 2, 3, 7, 16, 33, 1000])
+@pytest.mark.parametrize("K", [2, 5])
+def test_band_heights(band, K):
+    W, H = 512, 66
+    say("band", band, K)
+    rng = np.random.default_rng(band * 10 + K)
+    st = make_state(rng, W, H, "solid-particles")
+    s = Sim(W, H, seed=2, force_rate=1e-2, depth=K, band=min(band, H))
+    s.set_state(st, 0)
+    s.step(3 * K)
+    ref, _ = oracle.run(st, 0, 3 * K, 2, 1e-2, threads=THREADS)
+    np.testing.assert_array_equal(s.get_state(), ref)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 4])
+def test_depth_does_not_change_workload_result(K):
+    # The channel workload at reduced size, 48 steps: every depth gives the
+    # oracle's state.
+    wl = WL.CHANNEL
+    W, H = 2048, 256
+    s = Sim(W, H, seed=wl.seed, fill=wl.fill, force_rate=wl.force_rate, walls=True, depth=K)
+    s.step(48)
+    ref = oracle.init(W, H, wl.seed, wl.fill, walls=True)
+    ref, _ = oracle.run(ref, 0, 48, wl.seed, wl.force_rate, threads=THREADS)
+    np.testing.assert_array_equal(s.get_state(), ref)
+
+
+def test_fixed_points_blocked():
+    for v in (0x00, 0x7F):
+        s = Sim(256, 20, seed=4, depth=4)
+        s.set_state(np.full((20, 256), v, np.uint8), 0)
+        s.step(9)
+        assert np.all(s.get_state() == v)
