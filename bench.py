@@ -69,6 +69,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--depth", type=int, default=0, help="temporal-block depth k (0 = default)")
+    ap.add_argument("--band", type=int, default=0, help="rows per workgroup band (0 = default)")
     ap.add_argument("--workload", default="porous-16384")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -90,7 +91,7 @@ def main() -> int:
     mask = wl.mask()
     solid_frac = float(mask.mean()) if mask is not None else 0.0
 
-    warm = Sim(**wl.params(), solid=mask, depth=args.depth)
+    warm = Sim(**wl.params(), solid=mask, depth=args.depth, band=args.band)
     depth = warm.depth
     log(f"bench: warmup {args.warmup} steps at depth {depth}")
     warm.step(args.warmup)
@@ -98,7 +99,7 @@ def main() -> int:
     warm.close()
     del warm
 
-    sim = Sim(**wl.params(), solid=mask, depth=depth)
+    sim = Sim(**wl.params(), solid=mask, depth=depth, band=args.band)
     nodes = wl.width * wl.height
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -146,7 +147,7 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": wl.name, "width": wl.width, "height": wl.height,
                    "fill": wl.fill, "force_rate": wl.force_rate,
-                   "solid_fraction": round(solid_frac, 5), "depth": depth,
+                   "solid_fraction": round(solid_frac, 5), "depth": depth, "band": args.band,
                    "parity_digest_vs_oracle": parity},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,

@@ -62,7 +62,7 @@ extern "C" {
 #endif
 
 #define FHP_ABI_VERSION 1u
-#define FHP_MAX_DEPTH 8u /* largest temporal-block depth k of one HBM pass */
+#define FHP_MAX_DEPTH 4u /* largest temporal-block depth k of one HBM pass */
 
 enum {
     FHP_OK = 0,
@@ -93,7 +93,7 @@ enum {
 typedef struct fhp_params {
     uint32_t abi_version; /* FHP_ABI_VERSION */
     uint32_t width;       /* W: multiple of 64, < 2^20 */
-    uint32_t height;      /* H: even, >= 2, < 2^20 */
+    uint32_t height;      /* H: even, >= 2, < 2^20; W*H < 2^35 */
     uint32_t walls;       /* FHP_WALLS_* */
     uint32_t chirality;   /* FHP_CHIR_*; ZERO and ONE are test modes */
     uint32_t reserved;    /* must be 0 */

@@ -56,6 +56,9 @@ int validate(const fhp_params* p) {
         return fail(FHP_E_INVAL, "width %u must be a positive multiple of 64 below 2^20", p->width);
     if (p->height < 2 || p->height % 2 || p->height >= (1u << 20))
         return fail(FHP_E_INVAL, "height %u must be even, >= 2 and below 2^20", p->height);
+    if ((uint64_t)p->width * p->height >= (1ull << 35))
+        return fail(FHP_E_INVAL, "lattice of %llu nodes: a bit-plane must stay below 4 GiB",
+                    (unsigned long long)p->width * p->height);
     if (p->walls > FHP_WALLS_CHANNEL) return fail(FHP_E_INVAL, "walls %u unknown", p->walls);
     if (p->chirality > FHP_CHIR_ONE) return fail(FHP_E_INVAL, "chirality %u unknown", p->chirality);
     if (p->reserved) return fail(FHP_E_INVAL, "reserved field must be 0");
@@ -75,11 +78,14 @@ Layout layout_for(uint32_t W, uint32_t H) {
     return l;
 }
 
-// Default temporal-block depth: two steps per HBM pass where the blocked
-// kernel applies (full-row workgroups need at most 1024 words per row).
-uint32_t default_depth(uint32_t wd) { return wd <= kMaxBlockedWords ? 2 : 1; }
+// Default temporal-block depth where the blocked kernel applies (full-row
+// workgroups, at most kMaxBlockedWords words per row).  On the 16384^2 porous
+// lattice four steps per pass are fastest: the pass is then bound by VALU
+// work rather than by HBM traffic.
+uint32_t default_depth(uint32_t wd) { return wd <= kMaxBlockedWords ? 4 : 1; }
 
-// Default band height of the blocked kernel.
+// Default band height of the blocked kernel: 32 rows balances the halo rows
+// read twice (2K per band) against the number of workgroups in flight.
 uint32_t default_band(uint32_t H, uint32_t K) {
     (void)K;
     return H < 32 ? H : 32;

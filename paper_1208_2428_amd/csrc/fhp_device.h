@@ -32,61 +32,107 @@ FHP_HD uint64_t hash64(uint64_t key, uint64_t n) { return mix64(key + (n + 1) * 
 // Hash counter of (t, row, 64-node word): t*2^40 + y*2^20 + w.
 FHP_HD uint64_t counter(uint64_t t, uint64_t y, uint64_t w) { return (t << 40) + (y << 20) + w; }
 
-// FHP-II collision of 64 fluid nodes.  a[0..5] are the moving channels after
-// streaming, a[6] the rest channel, chi the chirality word.  Written as flip
-// masks: every rule moves the node between two states, so each output channel
-// is its input XOR the OR of the rules that touch it.  Indices are mod 6 for
-// channels and mod 3 for opposite pairs (pair j = channels j and j+3).
-//   R1 head-on pair j alone (no other moving particle): channels j, j+3 empty
-//      and the pair turned by +60 deg (chi=1) or -60 deg (chi=0) filled;
-//   R2 {0,2,4} <-> {1,3,5} with no rest particle: all six moving channels flip;
-//   R3 pattern (rest, c-1, c, c+1) = (1,0,1,0) or (0,1,0,1) with c+2, c+3,
-//      c+4 empty: channels c-1, c, c+1 and the rest channel flip.
-FHP_HD void collide(const uint64_t a[7], uint64_t chi, uint64_t o[7]) {
-    const uint64_t r = a[6];
-    uint64_t q[3], d[3], x[3];
-    for (int j = 0; j < 3; j++) {
-        q[j] = ~(a[j] | a[j + 3]);  // pair empty
-        x[j] = a[j] ^ a[j + 3];     // exactly one of the pair
-    }
-    for (int j = 0; j < 3; j++)     // head-on pair j and nothing else moving
-        d[j] = (a[j] & a[j + 3]) & q[(j + 1) % 3] & q[(j + 2) % 3];
-    // R2: one particle per pair and channels 0, 2, 4 equal, no rest particle.
-    const uint64_t eq024 = ~((a[0] ^ a[2]) | (a[0] ^ a[4]));
-    const uint64_t tri = ~r & x[0] & x[1] & x[2] & eq024;
-    // R1 flips per pair: the source pair, plus the target pair chosen by chi.
-    uint64_t f1[3];
-    for (int j = 0; j < 3; j++) {
-        const uint64_t tgt = (chi & d[(j + 2) % 3]) | (~chi & d[(j + 1) % 3]);
-        f1[j] = d[j] | tgt | tri;
-    }
-    // R3: g[c] marks nodes where the (c-1, c, c+1, rest) exchange applies.
-    uint64_t g[6];
-    for (int c = 0; c < 6; c++) {
-        const int cm = (c + 5) % 6, cp = (c + 1) % 6;
-        const uint64_t far_empty = ~(a[(c + 2) % 6] | a[(c + 3) % 6] | a[(c + 4) % 6]);
-        g[c] = far_empty & (r ^ a[cm]) & (a[c] ^ a[cm]) & (a[c] ^ a[cp]);
-    }
-    uint64_t gany = 0;
-    for (int c = 0; c < 6; c++) {
-        o[c] = a[c] ^ f1[c % 3] ^ (g[(c + 5) % 6] | g[c] | g[(c + 1) % 6]);
-        gany |= g[c];
-    }
-    o[6] = r ^ gany;
+// The same hash split into a per-word and a per-row part, so that a kernel
+// forms the SplitMix64 state with one 64-bit add:
+//   key + (t*2^40 + y*2^20 + w + 1)*gamma = word_base(key, w) + row_term(t, y)  (mod 2^64).
+FHP_HD uint64_t word_base(uint64_t key, uint64_t w) { return key + (w + 1) * kGamma; }
+FHP_HD uint64_t row_term(uint64_t t, uint64_t y) { return ((t << 40) + (y << 20)) * kGamma; }
+
+// Three-input bit function: bit i of the result is bit (a_i b_i c_i) of the
+// truth table TT, i.e. TT = f(0xF0, 0xCC, 0xAA).  One v_bitop3_b32 on gfx950.
+constexpr uint32_t kA = 0xF0, kB = 0xCC, kC = 0xAA;
+
+template <uint32_t TT>
+FHP_HD uint32_t lop3(uint32_t a, uint32_t b, uint32_t c) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_bitop3_b32(a, b, c, TT & 0xFF);
+#else
+    uint32_t r = 0;
+    for (uint32_t i = 0; i < 8; i++)
+        if ((TT >> i) & 1) r |= ((i & 4) ? a : ~a) & ((i & 2) ? b : ~b) & ((i & 1) ? c : ~c);
+    return r;
+#endif
 }
 
-// Full per-word update after streaming: collision on fluid nodes, bounce-back
-// c_i -> c_{i+3} on solid nodes (rest particle kept), then the forcing swap
-// of bits 5 -> 2 on fluid nodes selected by `coin` (one bit at most).
+FHP_HD uint32_t mux3(uint32_t s, uint32_t x, uint32_t y) {  // s ? x : y
+    return lop3<(kA & kB) | (~kA & kC)>(s, x, y);
+}
+FHP_HD uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
+    return lop3<(kA & kB) | (kA & kC) | (kB & kC)>(a, b, c);
+}
+FHP_HD uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) { return lop3<kA ^ kB ^ kC>(a, b, c); }
+FHP_HD uint32_t or3(uint32_t a, uint32_t b, uint32_t c) { return lop3<kA | kB | kC>(a, b, c); }
+
+// Update of 32 nodes after streaming (FHP-II collision on fluid nodes,
+// bounce-back on solid nodes, then forcing).  a[0..5] moving channels, a[6]
+// rest, s solid, chi chirality, coin forcing coin (at most one bit).
+//
+// Every colliding state maps to a function of the two channels next to each
+// output channel j (indices mod 6):
+//   R1 head-on pair alone (rest particle a spectator): the pair turns by
+//      +60 deg (chi = 1) or -60 deg (chi = 0): o_j = chi ? a_{j-1} : a_{j+1};
+//   R2 {0,2,4} <-> {1,3,5} without rest particle: o_j = a_{j-1} (= a_{j+1});
+//   R3 one particle c plus rest -> {c-1, c+1}: o_j = a_{j-1} | a_{j+1}, and
+//      {c-1, c+1} without rest -> c plus rest: o_j = a_{j-1} & a_{j+1};
+//      i.e. o_j = maj(rest, a_{j-1}, a_{j+1}) and the rest bit flips.
+// The rule that applies is found from the number n of moving particles
+// (a full-adder tree), whether an opposite pair is present (P) and whether
+// two neighbouring channels are occupied (adj): R1 = (n = 2) & P;
+// R3 = rest ? (n = 1) : ((n = 2) & !P & !adj); R2 = (n = 3), no rest,
+// channels 0, 2, 4 equal.
+FHP_HD void update32(const uint32_t a[7], uint32_t s, uint32_t chi, uint32_t coin, uint32_t o[7]) {
+    const uint32_t r = a[6];
+    // popcount of the six moving channels: n = n0 + 2 n1 + 4 n2
+    const uint32_t sa = xor3(a[0], a[1], a[2]), ca = maj3(a[0], a[1], a[2]);
+    const uint32_t sb = xor3(a[3], a[4], a[5]), cb = maj3(a[3], a[4], a[5]);
+    const uint32_t n0 = sa ^ sb, c0 = sa & sb;
+    const uint32_t n1 = xor3(ca, cb, c0), n2 = maj3(ca, cb, c0);
+    const uint32_t is1 = lop3<kA & ~kB & ~kC>(n0, n1, n2);
+    const uint32_t is2 = lop3<~kA & kB & ~kC>(n0, n1, n2);
+    const uint32_t is3 = lop3<kA & kB & ~kC>(n0, n1, n2);
+    // an opposite (head-on) pair is present
+    uint32_t pp = a[0] & a[3];
+    pp = lop3<kA | (kB & kC)>(pp, a[1], a[4]);
+    pp = lop3<kA | (kB & kC)>(pp, a[2], a[5]);
+    // two neighbouring channels are occupied
+    const uint32_t t1 = lop3<(kA & kB) | (kB & kC)>(a[0], a[1], a[2]);
+    const uint32_t t2 = lop3<(kA & kB) | (kB & kC)>(a[2], a[3], a[4]);
+    const uint32_t t3 = lop3<(kA & kB) | (kB & kC)>(a[4], a[5], a[0]);
+    const uint32_t adj = or3(t1, t2, t3);
+    const uint32_t eq024 = lop3<(kA & kB & kC) | (~kA & ~kB & ~kC)>(a[0], a[2], a[4]);
+    const uint32_t tri = lop3<kA & kB & ~kC>(is3, eq024, r);          // R2
+    const uint32_t head = is2 & pp;                                    // R1
+    const uint32_t v120 = lop3<kA & ~kB & ~kC>(is2, pp, adj);         // two at 120 deg
+    const uint32_t c12 = lop3<(kA | kB) & ~kC>(head, tri, s);         // R1 or R2, fluid
+    const uint32_t c3 = lop3<((kA & kB) | (~kA & kC)) & 0xFF>(r, is1, v120) & ~s;  // R3, fluid
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        const uint32_t am = a[(j + 5) % 6], ap = a[(j + 1) % 6];
+        const uint32_t rot = mux3(chi, am, ap);
+        const uint32_t r3 = maj3(r, am, ap);
+        const uint32_t base = mux3(s, a[(j + 3) % 6], a[j]);  // bounce-back or unchanged
+        o[j] = mux3(c12, rot, mux3(c3, r3, base));
+    }
+    o[6] = r ^ c3;
+    // forcing: bits 5 -> 2 where the coin is up, on fluid nodes with o5 set, o2 clear
+    const uint32_t cf = coin & ~s;
+    const uint32_t o5 = lop3<kA & ~(kB & ~kC)>(o[5], cf, o[2]);
+    const uint32_t o2 = lop3<kA | (kB & kC)>(o[2], cf, o[5]);
+    o[5] = o5;
+    o[2] = o2;
+}
+
+// 64-node version: the two 32-bit halves independently.
 FHP_HD void update(const uint64_t a[7], uint64_t solid, uint64_t chi, uint64_t coin,
                    uint64_t o[7]) {
-    uint64_t c[7];
-    collide(a, chi, c);
-    for (int i = 0; i < 6; i++) o[i] = (solid & a[(i + 3) % 6]) | (~solid & c[i]);
-    o[6] = (solid & a[6]) | (~solid & c[6]);
-    const uint64_t m = coin & ~solid & o[5] & ~o[2];
-    o[5] ^= m;
-    o[2] ^= m;
+    uint32_t lo[7], hi[7], olo[7], ohi[7];
+    for (int c = 0; c < 7; c++) {
+        lo[c] = (uint32_t)a[c];
+        hi[c] = (uint32_t)(a[c] >> 32);
+    }
+    update32(lo, (uint32_t)solid, (uint32_t)chi, (uint32_t)coin, olo);
+    update32(hi, (uint32_t)(solid >> 32), (uint32_t)(chi >> 32), (uint32_t)(coin >> 32), ohi);
+    for (int c = 0; c < 7; c++) o[c] = ((uint64_t)ohi[c] << 32) | olo[c];
 }
 
 // Forcing coin word: h = H(key_force, counter); the coin of node h>>58 is up

@@ -1,16 +1,18 @@
 // fhp_stepk.hip -- temporally blocked FHP update: K time steps per pass over
 // HBM (K = 1..FHP_MAX_DEPTH).
 //
-// Decomposition.  A workgroup owns a band of T consecutive rows and the full
-// lattice width: thread w holds 64-node word w of every row it touches, so
-// the periodic wrap in x needs no halo words.  The band sweeps downwards
-// through rows y0-K .. y0+T+K-1 of the input buffer, one row per iteration.
-// Level 0 is the loaded row; level l (1..K) is the state after l steps, and
-// its row rho = r - l is computed as soon as level l-1 has produced rows
-// rho-1, rho and rho+1 (pull streaming reads exactly those).  Each level
-// keeps the last two rows of the level below it in registers, so every input
-// row is read from HBM once per band and only the 2K halo rows are read twice
-// (by the neighbouring bands).  Level K rows y0 .. y0+T-1 are stored.
+// Decomposition.  A workgroup owns a band of T consecutive rows (T even) and
+// the full lattice width: thread w holds 64-node word w of every row it
+// touches, so the periodic wrap in x needs no halo words.  The band sweeps
+// downwards through rows y0-K .. y0+T+K-1 of the input buffer, one row per
+// iteration.  Level 0 is the loaded row; level l (1..K) is the state after l
+// steps, and its row rho = r - l is computed as soon as level l-1 has
+// produced rows rho-1, rho and rho+1 (pull streaming reads exactly those).
+// Each level keeps the last two rows of the level below it in registers, so
+// every input row is read from HBM once per band and only the 2K halo rows
+// are read twice (by the neighbouring bands).  Level K rows y0 .. y0+T-1 are
+// stored.  The first 2K iterations fill the pipeline; after that every
+// iteration produces one row of every level.
 //
 // Horizontal carries.  A 1-node shift of a word needs one bit of the
 // neighbouring word: bit 63 of the left word for rotl1, bit 0 of the right
@@ -19,14 +21,31 @@
 // each thread reads its two neighbours' dwords (wrapping at the row ends).
 // Two LDS slots alternate so that one barrier per exchange suffices.
 //
+// Row parity.  Odd rows are shifted by +1/2, so which planes shift depends on
+// the parity of the destination row.  With y0 and H even it equals the
+// parity of (i + K + l) for iteration i and level l; the sweep is unrolled by
+// two so that parity is a compile-time constant in every level.
+//
 // Time: level l of a pass starting at t0 applies step t0 + l - 1 (hash
 // counters use that t and the absolute row index, so results do not depend
-// on K or on the band size).
+// on K or on the band height).
+#include <type_traits>
+
 #include "fhp_device.h"
 #include "fhp_internal.h"
 
 namespace fhp {
 namespace {
+
+struct StepkArgs {
+    uint32_t H, wd;        // rows, words per row
+    uint32_t T;            // band height (even)
+    uint32_t walls;        // rows 0 and H-1 solid
+    uint64_t ps;           // plane stride in words
+    uint64_t t0;           // steps done before this pass
+    uint64_t key_chir, key_force, thr_force;
+    uint64_t chi_and, chi_or;  // chirality word = (hash & chi_and) | chi_or
+};
 
 // One row of one level, as seen by one thread.
 struct Row {
@@ -41,43 +60,58 @@ __device__ __forceinline__ uint64_t rotr1(uint64_t v, uint32_t cin) {
     return (v >> 1) | ((uint64_t)cin << 63);
 }
 
+// Calls f(integral_constant<int, I>) for I = L .. N.
+template <int L, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (L <= N) {
+        f(std::integral_constant<int, L>{});
+        static_for<L + 1, N>(f);
+    }
+}
+
 // Workgroup barrier that orders LDS traffic only: global loads issued for the
 // next row stay in flight across it.
 __device__ __forceinline__ void lds_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-template <int K>
+template <int K, bool FORCE, bool MASK>
 __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
-                                                uint64_t* __restrict__ out, Lattice L, Dyn D,
-                                                uint64_t t0, uint32_t T) {
+                                                uint64_t* __restrict__ out,
+                                                const uint64_t* __restrict__ S, StepkArgs a) {
     extern __shared__ uint32_t xch[];  // 2 slots x blockDim.x dwords
     const uint32_t nt = blockDim.x;
     const uint32_t lane = threadIdx.x;
-    const bool valid = lane < L.wd;
+    const bool valid = lane < a.wd;
     const uint32_t w = valid ? lane : 0;
-    const uint32_t wl = w ? w - 1 : L.wd - 1;
-    const uint32_t wr = (w + 1 == L.wd) ? 0 : w + 1;
-    const uint32_t H = L.H;
-    const uint32_t y0 = blockIdx.x * T;
-    const uint32_t rows = min(T, H - y0);
+    const uint32_t wl = w ? w - 1 : a.wd - 1;
+    const uint32_t wr = (w + 1 == a.wd) ? 0 : w + 1;
+    const uint32_t H = a.H;
+    const uint32_t y0 = blockIdx.x * a.T;
+    const uint32_t rows = min(a.T, H - y0);
     const int n_iter = (int)rows + 2 * K;
-    const size_t ps = L.ps;
+    const uint64_t base_chi = word_base(a.key_chir, w);
+    const uint64_t base_frc = word_base(a.key_force, w);
 
-    auto wrap_row = [&](int r) -> uint32_t {
+    auto wrap_row = [&](int r) __attribute__((always_inline)) -> uint32_t {
         int m = r % (int)H;
         return (uint32_t)(m < 0 ? m + (int)H : m);
     };
-    // Issues the loads of row y; the wall rows are applied when the row is
+    // Byte offset of word w of row y within a plane (planes are < 4 GiB).
+    auto offset = [&](uint32_t y) __attribute__((always_inline)) -> uint32_t { return (y * a.wd + w) * 8u; };
+    auto plane_in = [&](int c, uint32_t off) __attribute__((always_inline)) -> uint64_t {
+        return *(const uint64_t*)((const char*)(in + c * a.ps) + off);
+    };
+    // Issues the loads of row y; wall rows are applied when the row is
     // consumed, so that nothing waits on these loads before the next row.
-    auto load = [&](uint32_t y, Row& x) {
-        const size_t base = (size_t)y * L.wd + w;
+    auto load = [&](uint32_t y, Row& x) __attribute__((always_inline)) {
+        const uint32_t off = offset(y);
 #pragma unroll
-        for (int c = 0; c < 7; c++) x.p[c] = in[c * ps + base];
-        x.s = L.S ? L.S[base] : 0ull;
+        for (int c = 0; c < 7; c++) x.p[c] = plane_in(c, off);
+        if (MASK) x.s = *(const uint64_t*)((const char*)S + off);
     };
     uint32_t slot = 0;
-    auto exchange = [&](Row& x) {
+    auto exchange = [&](Row& x) __attribute__((always_inline)) {
         const uint32_t bits = (uint32_t)(x.p[1] >> 63) | ((uint32_t)(x.p[2] >> 63) << 1) |
                               ((uint32_t)(x.p[3] >> 63) << 2) | ((uint32_t)(x.p[0] & 1) << 8) |
                               ((uint32_t)(x.p[4] & 1) << 9) | ((uint32_t)(x.p[5] & 1) << 10);
@@ -88,87 +122,140 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
         slot ^= 1;
     };
 
-    Row A[K + 1], B[K + 1];  // level l input rows rho-1 (A) and rho (B), from level l-1
+    // Level l keeps two rows of level l-1: rho-1 (only planes 3, 4 and its carry
+    // bits are read again) and rho (everything).  Flat arrays indexed by
+    // compile-time levels stay in registers.
+    uint64_t a3[K + 1], a4[K + 1], bp[K + 1][7], bs[K + 1];
+    uint32_t ac[K + 1], bc[K + 1];
+    auto push = [&](auto lc, const Row& x) __attribute__((always_inline)) {
+        constexpr int l = decltype(lc)::value;
+        a3[l] = bp[l][3];
+        a4[l] = bp[l][4];
+        ac[l] = bc[l];
+#pragma unroll
+        for (int c = 0; c < 7; c++) bp[l][c] = x.p[c];
+        bs[l] = x.s;
+        bc[l] = x.c;
+    };
     Row nxt;
     load(wrap_row((int)y0 - K), nxt);
-    for (int i = 0; i < n_iter; i++) {
+
+    // One sweep iteration.  FULL: every level is active (i >= 2K).  PAR: i & 1.
+    auto body = [&](int i, auto full_c, auto par_c) __attribute__((always_inline)) {
+        constexpr bool FULL = decltype(full_c)::value;
+        constexpr int PAR = decltype(par_c)::value;
         const int r = (int)y0 - K + i;
+        const uint32_t y = wrap_row(r);
         Row X = nxt;
-        if (i + 1 < n_iter) load(wrap_row(r + 1), nxt);
-        {
-            const uint32_t y = wrap_row(r);
-            if (L.walls && (y == 0 || y == H - 1)) X.s = ~0ull;
-        }
+        // prefetch the next row (the last iteration reloads its own row)
+        load((i + 1 < n_iter) ? wrap_row(r + 1) : y, nxt);
+        uint64_t s = MASK ? X.s : 0ull;
+        if (a.walls && (y == 0 || y == H - 1)) s = ~0ull;
+        X.s = s;
         exchange(X);
         bool have = true;  // X holds a new row of level l-1
-#pragma unroll
-        for (int l = 1; l <= K; l++) {
-            if (!have) break;
-            if (i >= 2 * l) {
-                const uint32_t rho = wrap_row(r - l);
-                const bool odd = rho & 1;
-                const Row& a = A[l];
-                const Row& b = B[l];
-                uint64_t n[7];
-                n[3] = odd ? a.p[3] : rotl1(a.p[3], (a.c >> 2) & 1);
-                n[4] = odd ? rotr1(a.p[4], (a.c >> 9) & 1) : a.p[4];
-                n[2] = rotl1(b.p[2], (b.c >> 1) & 1);
-                n[5] = rotr1(b.p[5], (b.c >> 10) & 1);
-                n[6] = b.p[6];
-                n[0] = odd ? rotr1(X.p[0], (X.c >> 8) & 1) : X.p[0];
-                n[1] = odd ? X.p[1] : rotl1(X.p[1], X.c & 1);
-                const uint64_t tl = t0 + (uint64_t)(l - 1);
-                const uint64_t ctr = counter(tl, rho, w);
-                uint64_t chi;
-                if (D.chir_mode == FHP_CHIR_HASH) chi = hash64(D.key_chir, ctr);
-                else chi = (D.chir_mode == FHP_CHIR_ONE) ? ~0ull : 0ull;
-                const uint64_t coin =
-                    D.thr_force ? coin_word(hash64(D.key_force, ctr), D.thr_force) : 0ull;
-                Row Y;
-                update(n, b.s, chi, coin, Y.p);
-                Y.s = b.s;
-                A[l] = B[l];
-                B[l] = X;
-                if (l < K) {
-                    exchange(Y);
-                    X = Y;
-                } else if (valid) {
-                    const size_t base = (size_t)rho * L.wd + w;
-#pragma unroll
-                    for (int c = 0; c < 7; c++) out[c * ps + base] = Y.p[c];
+        static_for<1, K>([&](auto lc) __attribute__((always_inline)) {
+            constexpr int l = decltype(lc)::value;
+            if (!FULL) {
+                if (!have) return;
+                if (i < 2 * l) {
+                    push(lc, X);
+                    have = false;
+                    return;
                 }
-            } else {
-                A[l] = B[l];
-                B[l] = X;
-                have = false;
             }
-        }
+            const uint32_t rho = wrap_row(r - l);
+            constexpr bool odd = ((PAR + K + l) & 1) != 0;  // parity of rho
+            uint64_t n[7];
+            if (odd) {
+                n[3] = a3[l];
+                n[4] = rotr1(a4[l], (ac[l] >> 9) & 1);
+                n[0] = rotr1(X.p[0], (X.c >> 8) & 1);
+                n[1] = X.p[1];
+            } else {
+                n[3] = rotl1(a3[l], (ac[l] >> 2) & 1);
+                n[4] = a4[l];
+                n[0] = X.p[0];
+                n[1] = rotl1(X.p[1], X.c & 1);
+            }
+            n[2] = rotl1(bp[l][2], (bc[l] >> 1) & 1);
+            n[5] = rotr1(bp[l][5], (bc[l] >> 10) & 1);
+            n[6] = bp[l][6];
+            const uint64_t sw = bs[l];
+            const uint64_t R = row_term(a.t0 + (uint64_t)(l - 1), rho);
+            const uint64_t chi = (mix64(base_chi + R) & a.chi_and) | a.chi_or;
+            const uint64_t coin = FORCE ? coin_word(mix64(base_frc + R), a.thr_force) : 0ull;
+            Row Y;
+            update(n, sw, chi, coin, Y.p);
+            Y.s = sw;
+            push(lc, X);
+            if (l < K) {
+                exchange(Y);
+                X = Y;
+            } else if (valid) {
+                const uint32_t off = offset(rho);
+#pragma unroll
+                for (int c = 0; c < 7; c++) *(uint64_t*)((char*)(out + c * a.ps) + off) = Y.p[c];
+            }
+        });
+    };
+
+    using F = std::false_type;
+    using T = std::true_type;
+    using P0 = std::integral_constant<int, 0>;
+    using P1 = std::integral_constant<int, 1>;
+    int i = 0;
+    for (; i < 2 * K; i += 2) {  // pipeline fill (n_iter >= 2K + 2)
+        body(i, F{}, P0{});
+        body(i + 1, F{}, P1{});
+    }
+    for (; i < n_iter; i += 2) {  // rows is even, so n_iter - 2K is even
+        body(i, T{}, P0{});
+        body(i + 1, T{}, P1{});
     }
 }
 
-template <int K>
-hipError_t launch_k(const uint64_t* in, uint64_t* out, const Lattice& L, const Dyn& D, uint64_t t,
-                    uint32_t T, hipStream_t st) {
+template <int K, bool FORCE, bool MASK>
+hipError_t launch_k(const uint64_t* in, uint64_t* out, const Lattice& L, const StepkArgs& a,
+                    hipStream_t st) {
     const uint32_t nt = (L.wd + 63) / 64 * 64;
-    const uint32_t bands = (L.H + T - 1) / T;
-    hipLaunchKernelGGL(k_stepk<K>, dim3(bands), dim3(nt), 2 * nt * sizeof(uint32_t), st, in, out,
-                       L, D, t, T);
+    const uint32_t bands = (L.H + a.T - 1) / a.T;
+    hipLaunchKernelGGL((k_stepk<K, FORCE, MASK>), dim3(bands), dim3(nt), 2 * nt * sizeof(uint32_t),
+                       st, in, out, L.S, a);
     return hipGetLastError();
+}
+
+template <int K>
+hipError_t launch_k2(const uint64_t* in, uint64_t* out, const Lattice& L, const StepkArgs& a,
+                     hipStream_t st) {
+    const bool force = a.thr_force != 0, mask = L.S != nullptr;
+    if (force) return mask ? launch_k<K, true, true>(in, out, L, a, st)
+                           : launch_k<K, true, false>(in, out, L, a, st);
+    return mask ? launch_k<K, false, true>(in, out, L, a, st)
+                : launch_k<K, false, false>(in, out, L, a, st);
 }
 
 }  // namespace
 
 hipError_t launch_stepk(uint32_t K, const uint64_t* in, uint64_t* out, const Lattice& L,
                         const Dyn& D, uint64_t t, uint32_t T, hipStream_t st) {
+    StepkArgs a;
+    a.H = L.H;
+    a.wd = L.wd;
+    a.T = (T + 1) & ~1u;  // even, so that y0 is even
+    a.walls = L.walls;
+    a.ps = L.ps;
+    a.t0 = t;
+    a.key_chir = D.key_chir;
+    a.key_force = D.key_force;
+    a.thr_force = D.thr_force;
+    a.chi_and = (D.chir_mode == FHP_CHIR_HASH) ? ~0ull : 0ull;
+    a.chi_or = (D.chir_mode == FHP_CHIR_ONE) ? ~0ull : 0ull;
     switch (K) {
-        case 1: return launch_k<1>(in, out, L, D, t, T, st);
-        case 2: return launch_k<2>(in, out, L, D, t, T, st);
-        case 3: return launch_k<3>(in, out, L, D, t, T, st);
-        case 4: return launch_k<4>(in, out, L, D, t, T, st);
-        case 5: return launch_k<5>(in, out, L, D, t, T, st);
-        case 6: return launch_k<6>(in, out, L, D, t, T, st);
-        case 7: return launch_k<7>(in, out, L, D, t, T, st);
-        case 8: return launch_k<8>(in, out, L, D, t, T, st);
+        case 1: return launch_k2<1>(in, out, L, a, st);
+        case 2: return launch_k2<2>(in, out, L, a, st);
+        case 3: return launch_k2<3>(in, out, L, a, st);
+        case 4: return launch_k2<4>(in, out, L, a, st);
         default: return hipErrorInvalidValue;
     }
 }
