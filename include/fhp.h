@@ -154,8 +154,58 @@ int fhp_time(const fhp_sim *s, uint64_t *t);
 /* Waits for the handle's work; reports asynchronous device errors. */
 int fhp_sync(fhp_sim *s);
 
-/* Releases the handle (host memory only; the workspace stays the caller's). */
+/* Releases the handle (host memory only; the workspace stays the caller's).
+ * Does nothing for a batch member (released with its batch). */
 void fhp_destroy(fhp_sim *s);
+
+/* ---------------------------------------------------------------------------
+ * Batches: n independent lattices (any mix of sizes, seeds and parameters)
+ * advanced together by one persistent kernel.  Lattices are cut into bands of
+ * rows; bands of lattices with the same row width are packed side by side into
+ * one workgroup, and a persistent grid takes (pass, band group) work items from
+ * a device counter.  With more than one pass per launch, a band waits for its
+ * two neighbouring bands' previous pass (per-band counters on the device).
+ * Each member's results are identical to those of a standalone simulation with
+ * the same parameters (Sec. 2 model; the same readings as above).
+ * Members need width <= 32768 and height >= 2*FHP_MAX_DEPTH.
+ * ------------------------------------------------------------------------- */
+typedef struct fhp_batch fhp_batch;
+
+/* Device workspace for a batch of the n lattices ps[0..n-1]. */
+int fhp_batch_workspace_bytes(const fhp_params *ps, uint32_t n, size_t *bytes);
+
+/* Creates the batch at t = 0 (every member in its initial state), in dev_ws
+ * (caller-owned, 256-byte aligned, kept alive until fhp_batch_destroy).  All
+ * work goes to hip_stream; graph replay needs a stream other than the NULL
+ * stream.  Synchronises. */
+int fhp_batch_create(const fhp_params *ps, uint32_t n, void *dev_ws, size_t ws_bytes,
+                     void *hip_stream, fhp_batch **out);
+
+/* Tiling of the batch kernel: depth K (0 = FHP_MAX_DEPTH), target band height
+ * (0 = 32; per member the largest even divisor of H not above it and >= K),
+ * threads per workgroup (0 = smallest multiple of 64 holding the widest row),
+ * passes per launch (1 = one launch per pass; 0 = all passes of an
+ * fhp_batch_step call in one launch, ordered by per-band dependencies).
+ * Results do not depend on the tiling.  Synchronises. */
+int fhp_batch_set_tiling(fhp_batch *b, uint32_t depth, uint32_t band, uint32_t group_threads,
+                         uint32_t passes_per_launch);
+
+/* Graph replay of the launch sequence of fhp_batch_step (1 = on, the default). */
+int fhp_batch_set_graph(fhp_batch *b, int enable);
+
+/* Advances every member by n steps.  Asynchronous; FHP_E_STATE if a member's
+ * time would reach 2^24. */
+int fhp_batch_step(fhp_batch *b, uint64_t n);
+
+/* Handle of member i, usable with fhp_observe, fhp_get_state, fhp_set_state,
+ * fhp_time, fhp_step and fhp_sync; owned by the batch. */
+int fhp_batch_member(fhp_batch *b, uint32_t i, fhp_sim **view);
+
+/* Waits for the batch's work; FHP_E_DEVICE if a launch aborted. */
+int fhp_batch_sync(fhp_batch *b);
+
+/* Releases the batch and its member handles (not the workspace). */
+void fhp_batch_destroy(fhp_batch *b);
 
 #ifdef __cplusplus
 }

@@ -7,11 +7,14 @@ and fails loudly when it has not been built.
 from ._binding import (CHIR_HASH, CHIR_ONE, CHIR_ZERO, MAX_DEPTH, FhpError,  # noqa: F401
                        load)
 
-__all__ = ["Sim", "FhpError", "CHIR_HASH", "CHIR_ZERO", "CHIR_ONE", "MAX_DEPTH", "load"]
+__all__ = ["Sim", "Batch", "FhpError", "CHIR_HASH", "CHIR_ZERO", "CHIR_ONE", "MAX_DEPTH", "load"]
 
 
 def __getattr__(name):
     if name == "Sim":
         from .sim import Sim
         return Sim
+    if name == "Batch":
+        from .batch import Batch
+        return Batch
     raise AttributeError(name)

@@ -64,6 +64,19 @@ _SIGNATURES = {
     "fhp_time": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)]),
     "fhp_sync": (ctypes.c_int, [ctypes.c_void_p]),
     "fhp_destroy": (None, [ctypes.c_void_p]),
+    "fhp_batch_workspace_bytes": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_uint32,
+                                                 ctypes.POINTER(ctypes.c_size_t)]),
+    "fhp_batch_create": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_uint32, ctypes.c_void_p,
+                                        ctypes.c_size_t, ctypes.c_void_p,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "fhp_batch_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                            ctypes.c_uint32, ctypes.c_uint32]),
+    "fhp_batch_set_graph": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "fhp_batch_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "fhp_batch_member": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32,
+                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "fhp_batch_sync": (ctypes.c_int, [ctypes.c_void_p]),
+    "fhp_batch_destroy": (None, [ctypes.c_void_p]),
 }
 
 

@@ -1,4 +1,4 @@
-// fhp_api.hip -- the C ABI declared in include/fhp.h.
+// fhp_api.hip -- the single-lattice part of the C ABI declared in include/fhp.h.
 //
 // Host-side bookkeeping only: parameter validation, the workspace layout,
 // the time counter and the order of kernel launches.  Every step of the
@@ -12,11 +12,43 @@
 #include "fhp_device.h"
 #include "fhp_internal.h"
 
-using namespace fhp;
+namespace fhp {
 
 namespace {
-
 thread_local char g_err[512] = "";
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Bytes of the idle buffer, used as staging for host transfers.
+size_t staging_bytes(const fhp_sim* s) { return s->lay.buf_words * sizeof(uint64_t); }
+
+int refresh_has_mask(fhp_sim* s) {
+    FHP_HIP_TRY(launch_fill_u64(s->aux, 1, 0, s->st), "clear aux");
+    FHP_HIP_TRY(launch_or_reduce(s->S, (size_t)s->L.H * s->L.wd, s->aux, s->st), "mask reduce");
+    uint64_t any = 0;
+    FHP_HIP_TRY(hipMemcpyAsync(&any, s->aux, sizeof(any), hipMemcpyDeviceToHost, s->st), "copy");
+    FHP_HIP_TRY(hipStreamSynchronize(s->st), "sync");
+    s->has_mask = any != 0;
+    return FHP_OK;
+}
+
+// Uploads W*H bytes in row chunks through the idle buffer and packs them.
+int upload_bytes(fhp_sim* s, const uint8_t* host, int mask_only) {
+    const uint32_t W = s->L.W, H = s->L.H;
+    uint8_t* stage = (uint8_t*)s->buf[1 - s->cur];
+    uint32_t rows = (uint32_t)(staging_bytes(s) / W);
+    if (rows > H) rows = H;
+    for (uint32_t r0 = 0; r0 < H; r0 += rows) {
+        const uint32_t n = (r0 + rows <= H) ? rows : H - r0;
+        FHP_HIP_TRY(hipMemcpyAsync(stage, host + (size_t)r0 * W, (size_t)n * W,
+                                   hipMemcpyHostToDevice, s->st), "upload");
+        FHP_HIP_TRY(launch_pack(stage, r0, n, s->L, s->buf[s->cur], s->S, mask_only, s->st),
+                    "pack");
+        FHP_HIP_TRY(hipStreamSynchronize(s->st), "sync");  // the stage is reused
+    }
+    return FHP_OK;
+}
+}  // namespace
 
 int fail(int code, const char* fmt, ...) {
     va_list ap;
@@ -29,24 +61,6 @@ int fail(int code, const char* fmt, ...) {
 int hip_fail(hipError_t e, const char* what) {
     return fail(FHP_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
-
-#define HIP_TRY(expr, what)                      \
-    do {                                         \
-        hipError_t e_ = (expr);                  \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
-    } while (0)
-
-constexpr uint64_t kTimeLimit = 1ull << 24;  // t*2^40 must stay below 2^64
-constexpr size_t kAuxWords = 512;            // reduction scratch
-
-size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-// Workspace layout: [buffer 0: 7 planes][buffer 1: 7 planes][S plane][aux].
-struct Layout {
-    size_t plane_words;  // padded words per plane
-    size_t buf_words;    // 7 planes
-    size_t s_off, aux_off, total_bytes;
-};
 
 int validate(const fhp_params* p) {
     if (!p) return fail(FHP_E_INVAL, "params is NULL");
@@ -91,67 +105,57 @@ uint32_t default_band(uint32_t H, uint32_t K) {
     return H < 32 ? H : 32;
 }
 
-}  // namespace
-
-struct fhp_sim {
-    fhp_params p;
-    Lattice L;       // L.S is set per launch from has_mask
-    Dyn D;
-    Layout lay;
-    uint64_t* ws;
-    uint64_t* buf[2];
-    uint64_t* S;
-    uint64_t* aux;
-    int cur;
-    uint64_t t;
-    uint32_t depth;  // temporal-block depth K
-    uint32_t band;   // rows per workgroup of the blocked kernel
-    int has_mask;
-    hipStream_t st;
-};
-
-namespace {
-
 Lattice lattice_of(const fhp_sim* s) {
     Lattice L = s->L;
     L.S = s->has_mask ? s->S : nullptr;
     return L;
 }
 
-// Bytes of the idle buffer, used as staging for host transfers.
-size_t staging_bytes(const fhp_sim* s) { return s->lay.buf_words * sizeof(uint64_t); }
+int sim_setup(fhp_sim* s, const fhp_params* p, uint64_t* planes, const Layout& lay,
+              uint64_t* aux, hipStream_t st) {
+    s->p = *p;
+    s->p.solid = nullptr;
+    s->lay = lay;
+    s->buf[0] = planes;
+    s->buf[1] = planes + lay.buf_words;
+    s->S = planes + lay.s_off;
+    s->aux = aux;
+    s->cur = 0;
+    s->t = 0;
+    s->st = st;
+    s->L.W = p->width;
+    s->L.H = p->height;
+    s->L.wd = p->width / 64;
+    s->L.ps = lay.plane_words;
+    s->L.walls = p->walls == FHP_WALLS_CHANNEL;
+    s->D.key_chir = hash64(p->seed, kTagChir);
+    s->D.key_force = hash64(p->seed, kTagForce);
+    s->D.thr_force = (uint64_t)floor(p->force_rate * 274877906944.0);  // f * 2^38
+    s->D.chir_mode = p->chirality;
+    s->depth = default_depth(s->L.wd);
+    s->band = 0;
 
-int refresh_has_mask(fhp_sim* s) {
-    HIP_TRY(launch_fill_u64(s->aux, 1, 0, s->st), "clear aux");
-    HIP_TRY(launch_or_reduce(s->S, (size_t)s->L.H * s->L.wd, s->aux, s->st), "mask reduce");
-    uint64_t any = 0;
-    HIP_TRY(hipMemcpyAsync(&any, s->aux, sizeof(any), hipMemcpyDeviceToHost, s->st), "copy");
-    HIP_TRY(hipStreamSynchronize(s->st), "sync");
-    s->has_mask = any != 0;
-    return FHP_OK;
-}
-
-// Uploads W*H bytes in row chunks through the idle buffer and packs them.
-int upload_bytes(fhp_sim* s, const uint8_t* host, int mask_only) {
-    const uint32_t W = s->L.W, H = s->L.H;
-    uint8_t* stage = (uint8_t*)s->buf[1 - s->cur];
-    uint32_t rows = (uint32_t)(staging_bytes(s) / W);
-    if (rows > H) rows = H;
-    for (uint32_t r0 = 0; r0 < H; r0 += rows) {
-        const uint32_t n = (r0 + rows <= H) ? rows : H - r0;
-        HIP_TRY(hipMemcpyAsync(stage, host + (size_t)r0 * W, (size_t)n * W, hipMemcpyHostToDevice,
-                               s->st), "upload");
-        HIP_TRY(launch_pack(stage, r0, n, s->L, s->buf[s->cur], s->S, mask_only, s->st), "pack");
-        HIP_TRY(hipStreamSynchronize(s->st), "sync");  // the stage is reused
+    FHP_HIP_TRY(launch_fill_u64(s->S, lay.plane_words, 0, st), "clear solid plane");
+    if (p->solid) {
+        int r = upload_bytes(s, p->solid, 1);
+        if (r) return r;
     }
+    int r = refresh_has_mask(s);
+    if (r) return r;
+    const uint64_t thr_fill = (uint64_t)floor(p->fill * 4294967296.0);  // fill * 2^32
+    FHP_HIP_TRY(launch_init(s->buf[0], lattice_of(s), hash64(p->seed, kTagInit), thr_fill, st),
+                "init");
+    FHP_HIP_TRY(hipStreamSynchronize(st), "sync");
     return FHP_OK;
 }
 
-}  // namespace
+}  // namespace fhp
+
+using namespace fhp;
 
 extern "C" {
 
-const char* fhp_last_error(void) { return g_err; }
+const char* fhp_last_error(void) { return fhp::g_err; }
 
 int fhp_workspace_bytes(const fhp_params* p, size_t* bytes) {
     int rc = validate(p);
@@ -171,49 +175,13 @@ int fhp_create(const fhp_params* p, void* dev_ws, size_t ws_bytes, void* hip_str
     Layout lay = layout_for(p->width, p->height);
     if (ws_bytes < lay.total_bytes)
         return fail(FHP_E_NOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, lay.total_bytes);
-
     fhp_sim* s = (fhp_sim*)calloc(1, sizeof(fhp_sim));
     if (!s) return fail(FHP_E_NOMEM, "host allocation failed");
-    s->p = *p;
-    s->p.solid = nullptr;
-    s->lay = lay;
-    s->ws = (uint64_t*)dev_ws;
-    s->buf[0] = s->ws;
-    s->buf[1] = s->ws + lay.buf_words;
-    s->S = s->ws + lay.s_off;
-    s->aux = s->ws + lay.aux_off;
-    s->cur = 0;
-    s->t = 0;
-    s->depth = default_depth(s->L.wd);
-    s->band = 0;
-    s->st = (hipStream_t)hip_stream;
-    s->L.W = p->width;
-    s->L.H = p->height;
-    s->L.wd = p->width / 64;
-    s->L.ps = lay.plane_words;
-    s->L.walls = p->walls == FHP_WALLS_CHANNEL;
-    s->D.key_chir = hash64(p->seed, kTagChir);
-    s->D.key_force = hash64(p->seed, kTagForce);
-    s->D.thr_force = (uint64_t)floor(p->force_rate * 274877906944.0);  // f * 2^38
-    s->D.chir_mode = p->chirality;
-
-    int r = FHP_OK;
-    hipError_t e = launch_fill_u64(s->S, lay.plane_words, 0, s->st);
-    if (e != hipSuccess) r = hip_fail(e, "clear solid plane");
-    if (!r && p->solid) r = upload_bytes(s, p->solid, 1);
-    if (!r) r = refresh_has_mask(s);
-    if (!r) {
-        const uint64_t thr_fill = (uint64_t)floor(p->fill * 4294967296.0);  // fill * 2^32
-        e = launch_init(s->buf[0], lattice_of(s), hash64(p->seed, kTagInit), thr_fill, s->st);
-        if (e != hipSuccess) r = hip_fail(e, "init");
-    }
-    if (!r) {
-        e = hipStreamSynchronize(s->st);
-        if (e != hipSuccess) r = hip_fail(e, "sync");
-    }
-    if (r) {
+    uint64_t* ws = (uint64_t*)dev_ws;
+    rc = sim_setup(s, p, ws, lay, ws + lay.aux_off, (hipStream_t)hip_stream);
+    if (rc) {
         free(s);
-        return r;
+        return rc;
     }
     *out = s;
     return FHP_OK;
@@ -246,15 +214,18 @@ int fhp_step(fhp_sim* s, uint64_t n) {
     if (n >= kTimeLimit || s->t + n >= kTimeLimit)
         return fail(FHP_E_STATE, "time %llu + %llu would reach 2^24",
                     (unsigned long long)s->t, (unsigned long long)n);
+    if (s->changed && n) *s->changed = 1;
     const Lattice L = lattice_of(s);
     const uint32_t T = s->band ? s->band : default_band(s->L.H, s->depth);
     while (n > 0) {
         uint32_t k = (n >= s->depth) ? s->depth : (uint32_t)n;
         if (k == 1)
-            HIP_TRY(launch_step1(s->buf[s->cur], s->buf[1 - s->cur], L, s->D, s->t, s->st), "step");
+            FHP_HIP_TRY(launch_step1(s->buf[s->cur], s->buf[1 - s->cur], L, s->D, s->t, s->st),
+                        "step");
         else
-            HIP_TRY(launch_stepk(k, s->buf[s->cur], s->buf[1 - s->cur], L, s->D, s->t, T, s->st),
-                    "step");
+            FHP_HIP_TRY(
+                launch_stepk(k, s->buf[s->cur], s->buf[1 - s->cur], L, s->D, s->t, T, s->st),
+                "step");
         s->cur ^= 1;
         s->t += k;
         n -= k;
@@ -268,12 +239,15 @@ int fhp_observe(fhp_sim* s, int kind, uint32_t block, void* host_dst, size_t dst
     const uint64_t* planes = s->buf[s->cur];
     if (kind == FHP_OBS_GLOBAL || kind == FHP_OBS_DIGEST) {
         const size_t need = (kind == FHP_OBS_GLOBAL ? 11 : 1) * sizeof(uint64_t);
-        if (dst_bytes < need) return fail(FHP_E_NOMEM, "destination of %zu bytes, %zu needed", dst_bytes, need);
-        HIP_TRY(launch_fill_u64(s->aux, 11, 0, s->st), "clear aux");
-        if (kind == FHP_OBS_GLOBAL) HIP_TRY(launch_observe_global(planes, L, s->aux, s->st), "observe");
-        else HIP_TRY(launch_digest(planes, L, s->aux, s->st), "digest");
-        HIP_TRY(hipMemcpyAsync(host_dst, s->aux, need, hipMemcpyDeviceToHost, s->st), "copy");
-        HIP_TRY(hipStreamSynchronize(s->st), "sync");
+        if (dst_bytes < need)
+            return fail(FHP_E_NOMEM, "destination of %zu bytes, %zu needed", dst_bytes, need);
+        FHP_HIP_TRY(launch_fill_u64(s->aux, 11, 0, s->st), "clear aux");
+        if (kind == FHP_OBS_GLOBAL)
+            FHP_HIP_TRY(launch_observe_global(planes, L, s->aux, s->st), "observe");
+        else
+            FHP_HIP_TRY(launch_digest(planes, L, s->aux, s->st), "digest");
+        FHP_HIP_TRY(hipMemcpyAsync(host_dst, s->aux, need, hipMemcpyDeviceToHost, s->st), "copy");
+        FHP_HIP_TRY(hipStreamSynchronize(s->st), "sync");
         return FHP_OK;
     }
     if (kind != FHP_OBS_BLOCKS) return fail(FHP_E_INVAL, "unknown observable %d", kind);
@@ -288,10 +262,10 @@ int fhp_observe(fhp_sim* s, int kind, uint32_t block, void* host_dst, size_t dst
     if (rows > bh) rows = bh;
     for (uint32_t r0 = 0; r0 < bh; r0 += rows) {
         const uint32_t n = (r0 + rows <= bh) ? rows : bh - r0;
-        HIP_TRY(launch_observe_blocks(planes, L, block, r0, n, stage, s->st), "blocks");
-        HIP_TRY(hipMemcpyAsync((char*)host_dst + (size_t)r0 * row_bytes, stage, n * row_bytes,
-                               hipMemcpyDeviceToHost, s->st), "copy");
-        HIP_TRY(hipStreamSynchronize(s->st), "sync");
+        FHP_HIP_TRY(launch_observe_blocks(planes, L, block, r0, n, stage, s->st), "blocks");
+        FHP_HIP_TRY(hipMemcpyAsync((char*)host_dst + (size_t)r0 * row_bytes, stage, n * row_bytes,
+                                   hipMemcpyDeviceToHost, s->st), "copy");
+        FHP_HIP_TRY(hipStreamSynchronize(s->st), "sync");
     }
     return FHP_OK;
 }
@@ -299,17 +273,18 @@ int fhp_observe(fhp_sim* s, int kind, uint32_t block, void* host_dst, size_t dst
 int fhp_get_state(fhp_sim* s, uint8_t* host_dst, size_t bytes) {
     if (!s || !host_dst) return fail(FHP_E_INVAL, "NULL argument");
     const uint32_t W = s->L.W, H = s->L.H;
-    if (bytes < (size_t)W * H) return fail(FHP_E_NOMEM, "destination of %zu bytes, %zu needed", bytes, (size_t)W * H);
+    if (bytes < (size_t)W * H)
+        return fail(FHP_E_NOMEM, "destination of %zu bytes, %zu needed", bytes, (size_t)W * H);
     const Lattice L = lattice_of(s);
     uint8_t* stage = (uint8_t*)s->buf[1 - s->cur];
     uint32_t rows = (uint32_t)(staging_bytes(s) / W);
     if (rows > H) rows = H;
     for (uint32_t r0 = 0; r0 < H; r0 += rows) {
         const uint32_t n = (r0 + rows <= H) ? rows : H - r0;
-        HIP_TRY(launch_unpack(s->buf[s->cur], L, r0, n, stage, s->st), "unpack");
-        HIP_TRY(hipMemcpyAsync(host_dst + (size_t)r0 * W, stage, (size_t)n * W,
-                               hipMemcpyDeviceToHost, s->st), "download");
-        HIP_TRY(hipStreamSynchronize(s->st), "sync");
+        FHP_HIP_TRY(launch_unpack(s->buf[s->cur], L, r0, n, stage, s->st), "unpack");
+        FHP_HIP_TRY(hipMemcpyAsync(host_dst + (size_t)r0 * W, stage, (size_t)n * W,
+                                   hipMemcpyDeviceToHost, s->st), "download");
+        FHP_HIP_TRY(hipStreamSynchronize(s->st), "sync");
     }
     return FHP_OK;
 }
@@ -319,6 +294,7 @@ int fhp_set_state(fhp_sim* s, const uint8_t* host_src, size_t bytes, uint64_t t)
     if (bytes != (size_t)s->L.W * s->L.H)
         return fail(FHP_E_INVAL, "state of %zu bytes, %zu expected", bytes, (size_t)s->L.W * s->L.H);
     if (t >= kTimeLimit) return fail(FHP_E_STATE, "time %llu at or above 2^24", (unsigned long long)t);
+    if (s->changed) *s->changed = 1;
     int rc = upload_bytes(s, host_src, 0);
     if (rc) return rc;
     rc = refresh_has_mask(s);
@@ -335,13 +311,13 @@ int fhp_time(const fhp_sim* s, uint64_t* t) {
 
 int fhp_sync(fhp_sim* s) {
     if (!s) return fail(FHP_E_INVAL, "sim is NULL");
-    HIP_TRY(hipStreamSynchronize(s->st), "sync");
-    HIP_TRY(hipGetLastError(), "device");
+    FHP_HIP_TRY(hipStreamSynchronize(s->st), "sync");
+    FHP_HIP_TRY(hipGetLastError(), "device");
     return FHP_OK;
 }
 
 void fhp_destroy(fhp_sim* s) {
-    if (!s) return;
+    if (!s || s->owner) return;  // batch members are released with their batch
     (void)hipStreamSynchronize(s->st);
     free(s);
 }

@@ -25,6 +25,32 @@ struct Dyn {
     uint32_t chir_mode = 0;  // FHP_CHIR_*
 };
 
+// Workspace layout of one lattice: [buffer 0: 7 planes][buffer 1: 7 planes]
+// [S plane][aux].
+struct Layout {
+    size_t plane_words;  // padded words per plane
+    size_t buf_words;    // 7 planes
+    size_t s_off, aux_off, total_bytes;
+};
+
+constexpr uint64_t kTimeLimit = 1ull << 24;  // t*2^40 must stay below 2^64
+constexpr size_t kAuxWords = 512;            // reduction scratch (words)
+constexpr uint32_t kMaxBlockedWords = 512;   // widest row of the blocked kernels (words)
+
+// Error reporting: sets the calling thread's message, returns the code.
+int fail(int code, const char* fmt, ...);
+int hip_fail(hipError_t e, const char* what);
+#define FHP_HIP_TRY(expr, what)                                 \
+    do {                                                        \
+        hipError_t e_ = (expr);                                 \
+        if (e_ != hipSuccess) return ::fhp::hip_fail(e_, what); \
+    } while (0)
+
+int validate(const fhp_params* p);
+Layout layout_for(uint32_t W, uint32_t H);
+uint32_t default_depth(uint32_t wd);
+uint32_t default_band(uint32_t H, uint32_t K);
+
 // Kernel launchers (fhp_kernels.hip).  All enqueue on `st` and return the HIP
 // launch status.
 hipError_t launch_fill_u64(uint64_t* p, size_t n, uint64_t v, hipStream_t st);
@@ -46,6 +72,37 @@ hipError_t launch_step1(const uint64_t* in, uint64_t* out, const Lattice& L, con
 // Needs L.wd <= kMaxBlockedWords.
 hipError_t launch_stepk(uint32_t K, const uint64_t* in, uint64_t* out, const Lattice& L,
                         const Dyn& D, uint64_t t, uint32_t T, hipStream_t st);
-constexpr uint32_t kMaxBlockedWords = 512;
+
+}  // namespace fhp
+
+// One lattice.  A standalone simulation owns no device memory (the caller owns
+// the workspace); a batch member is a view into the batch workspace
+// (owner != nullptr), released with the batch.
+struct fhp_sim {
+    fhp_params p;
+    fhp::Lattice L;  // L.S is set per launch from has_mask
+    fhp::Dyn D;
+    fhp::Layout lay;
+    uint64_t* buf[2];
+    uint64_t* S;
+    uint64_t* aux;
+    int cur;         // buffer holding the current state
+    uint64_t t;      // steps completed
+    uint32_t depth;  // temporal-block depth K
+    uint32_t band;   // rows per workgroup of the blocked kernel (0 = default)
+    int has_mask;
+    hipStream_t st;
+    void* owner;     // batch that owns this view, or nullptr
+    int* changed;    // set to 1 when the state or time is changed through this handle
+};
+
+namespace fhp {
+
+// Fills in a simulation whose planes start at `planes` (layout `lay`) with
+// reduction scratch `aux`, uploads the mask and writes the initial state.
+// Synchronises the stream.
+int sim_setup(fhp_sim* s, const fhp_params* p, uint64_t* planes, const Layout& lay,
+              uint64_t* aux, hipStream_t st);
+Lattice lattice_of(const fhp_sim* s);
 
 }  // namespace fhp

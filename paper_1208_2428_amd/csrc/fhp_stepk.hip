@@ -29,10 +29,9 @@
 // Time: level l of a pass starting at t0 applies step t0 + l - 1 (hash
 // counters use that t and the absolute row index, so results do not depend
 // on K or on the band height).
-#include <type_traits>
-
 #include "fhp_device.h"
 #include "fhp_internal.h"
+#include "fhp_sweep.h"
 
 namespace fhp {
 namespace {
@@ -46,34 +45,6 @@ struct StepkArgs {
     uint64_t key_chir, key_force, thr_force;
     uint64_t chi_and, chi_or;  // chirality word = (hash & chi_and) | chi_or
 };
-
-// One row of one level, as seen by one thread.
-struct Row {
-    uint64_t p[7];  // planes
-    uint64_t s;     // solid word (obstacles + wall rows)
-    uint32_t c;     // carry-in bits: bit 0..2 = bit 63 of the left word's planes 1, 2, 3;
-                    // bit 8..10 = bit 0 of the right word's planes 0, 4, 5
-};
-
-__device__ __forceinline__ uint64_t rotl1(uint64_t v, uint32_t cin) { return (v << 1) | cin; }
-__device__ __forceinline__ uint64_t rotr1(uint64_t v, uint32_t cin) {
-    return (v >> 1) | ((uint64_t)cin << 63);
-}
-
-// Calls f(integral_constant<int, I>) for I = L .. N.
-template <int L, int N, class F>
-__device__ __forceinline__ void static_for(F&& f) {
-    if constexpr (L <= N) {
-        f(std::integral_constant<int, L>{});
-        static_for<L + 1, N>(f);
-    }
-}
-
-// Workgroup barrier that orders LDS traffic only: global loads issued for the
-// next row stay in flight across it.
-__device__ __forceinline__ void lds_barrier() {
-    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
 
 template <int K, bool FORCE, bool MASK>
 __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
@@ -111,16 +82,6 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
         if (MASK) x.s = *(const uint64_t*)((const char*)S + off);
     };
     uint32_t slot = 0;
-    auto exchange = [&](Row& x) __attribute__((always_inline)) {
-        const uint32_t bits = (uint32_t)(x.p[1] >> 63) | ((uint32_t)(x.p[2] >> 63) << 1) |
-                              ((uint32_t)(x.p[3] >> 63) << 2) | ((uint32_t)(x.p[0] & 1) << 8) |
-                              ((uint32_t)(x.p[4] & 1) << 9) | ((uint32_t)(x.p[5] & 1) << 10);
-        uint32_t* buf = xch + slot * nt;
-        buf[lane] = bits;
-        lds_barrier();
-        x.c = (buf[wl] & 0x7u) | (buf[wr] & 0x700u);
-        slot ^= 1;
-    };
 
     // Level l keeps two rows of level l-1: rho-1 (only planes 3, 4 and its carry
     // bits are read again) and rho (everything).  Flat arrays indexed by
@@ -152,7 +113,7 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
         uint64_t s = MASK ? X.s : 0ull;
         if (a.walls && (y == 0 || y == H - 1)) s = ~0ull;
         X.s = s;
-        exchange(X);
+        exchange(xch, slot, nt, lane, wl, wr, X);
         bool have = true;  // X holds a new row of level l-1
         static_for<1, K>([&](auto lc) __attribute__((always_inline)) {
             constexpr int l = decltype(lc)::value;
@@ -167,20 +128,7 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
             const uint32_t rho = wrap_row(r - l);
             constexpr bool odd = ((PAR + K + l) & 1) != 0;  // parity of rho
             uint64_t n[7];
-            if (odd) {
-                n[3] = a3[l];
-                n[4] = rotr1(a4[l], (ac[l] >> 9) & 1);
-                n[0] = rotr1(X.p[0], (X.c >> 8) & 1);
-                n[1] = X.p[1];
-            } else {
-                n[3] = rotl1(a3[l], (ac[l] >> 2) & 1);
-                n[4] = a4[l];
-                n[0] = X.p[0];
-                n[1] = rotl1(X.p[1], X.c & 1);
-            }
-            n[2] = rotl1(bp[l][2], (bc[l] >> 1) & 1);
-            n[5] = rotr1(bp[l][5], (bc[l] >> 10) & 1);
-            n[6] = bp[l][6];
+            stream_in<odd>(a3[l], a4[l], ac[l], bp[l], bc[l], X, n);
             const uint64_t sw = bs[l];
             const uint64_t R = row_term(a.t0 + (uint64_t)(l - 1), rho);
             const uint64_t chi = (mix64(base_chi + R) & a.chi_and) | a.chi_or;
@@ -190,7 +138,7 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
             Y.s = sw;
             push(lc, X);
             if (l < K) {
-                exchange(Y);
+                exchange(xch, slot, nt, lane, wl, wr, Y);
                 X = Y;
             } else if (valid) {
                 const uint32_t off = offset(rho);
