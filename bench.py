@@ -63,6 +63,39 @@ def cpu_baseline(wl, mask, seconds: float):
                       f"{steps} steps in {el:.1f} s"}
 
 
+def plain_rate(wl, mask, depth: int, steps: int) -> float:
+    """Node updates/s of the single-lattice kernel at depth `depth`."""
+    import torch
+
+    from paper_1208_2428_amd import Sim
+    sim = Sim(**wl.params(), solid=mask, depth=depth)
+    sim.step(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.close()
+    return wl.width * wl.height * steps / wall
+
+
+def batched_leg(args, wl, mask, depth, value):
+    """512 uneven lattices in one batch vs the plain single-lattice kernel."""
+    from paper_1208_2428_amd import ensemble
+    params = ensemble.ensemble_params()
+    log(f"bench: ensemble of {len(params)} lattices, {args.ensemble_steps} steps (tuning first)")
+    res = ensemble.run_batched(params, args.ensemble_steps, log=log)
+    k = res["tiling"]["depth"]
+    plain = value if k == depth else plain_rate(wl, mask, k, 240)
+    log(f"bench: ensemble {res['value']:.3e} node-updates/s at depth {k}; plain {plain:.3e}")
+    one = ensemble.run_one_by_one(params, args.ensemble_steps)
+    log(f"bench: ensemble one lattice at a time: {one['value']:.3e} node-updates/s")
+    return {"value": res["value"], "unit": "node-updates/s", "lattices": res["lattices"],
+            "nodes": res["nodes"], "steps": res["steps"], "tiling": res["tiling"],
+            "plain_value_same_depth": plain, "ratio_vs_plain": res["value"] / plain,
+            "one_by_one_value": one["value"], "ratio_vs_one_by_one": res["value"] / one["value"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +106,9 @@ def main() -> int:
     ap.add_argument("--workload", default="porous-16384")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="skip the 512-lattice batched ensemble comparison")
+    ap.add_argument("--ensemble-steps", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -153,6 +189,8 @@ def main() -> int:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel_us": launch_s * 1e6, "bytes_per_launch": bytes_per_launch},
     }
+    if not args.no_ensemble:
+        out["batched"] = batched_leg(args, wl, mask, depth, value)
     if not args.no_cpu_baseline:
         log(f"bench: timing the CPU oracle for ~{args.cpu_seconds:.0f} s")
         out["cpu_baseline"] = cpu_baseline(wl, mask, args.cpu_seconds)

@@ -230,12 +230,15 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
             body(i + 1, Tt{}, P1{});
         }
 
-        // publish this band's pass
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (active && w == 0)
-            __hip_atomic_fetch_add(done + M.done_off + b, 1u, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+        // Publish this band's pass to later passes of the same launch (with a
+        // single pass per launch the kernel boundary orders the passes).
+        if (passes > 1) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (active && w == 0)
+                __hip_atomic_fetch_add(done + M.done_off + b, 1u, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 
     // The last workgroup out advances the members and resets the counters.
