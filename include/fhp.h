@@ -207,6 +207,68 @@ int fhp_batch_sync(fhp_batch *b);
 /* Releases the batch and its member handles (not the workspace). */
 void fhp_batch_destroy(fhp_batch *b);
 
+/* ---------------------------------------------------------------------------
+ * Pools: continuous batching of simulation jobs that arrive and leave.  A pool
+ * owns a caller-provided device arena (the HBM budget); a job is admitted when
+ * a slot, arena memory and band-table room are free, stays resident until it
+ * is released, and advances with every tick together with all other resident
+ * jobs (one batch-kernel launch per pass over all of them, each job clipped to
+ * its remaining steps; the last steps that do not fill a pass run on the
+ * single-lattice kernels).  A job's result does not depend on the other jobs
+ * or on when it was admitted.  Members need width <= 32768 and height >= 8.
+ * ------------------------------------------------------------------------- */
+typedef struct fhp_pool fhp_pool;
+
+/* Arena size for max_slots jobs, max_bands bands of rows in total (a job of
+ * height H uses about H/32 bands) and lattice_bytes of lattice storage (a
+ * W x H job takes about 1.875*W*H bytes: two 7-plane buffers and an obstacle
+ * plane). */
+int fhp_pool_workspace_bytes(uint32_t max_slots, uint32_t max_bands, size_t lattice_bytes,
+                             size_t *bytes);
+
+/* Creates an empty pool in dev_arena (caller-owned, 256-byte aligned, kept
+ * alive until fhp_pool_destroy).  Work goes to hip_stream (not the NULL stream
+ * if ticks are to be graph-replayed). */
+int fhp_pool_create(void *dev_arena, size_t arena_bytes, uint32_t max_slots, uint32_t max_bands,
+                    void *hip_stream, fhp_pool **out);
+
+/* Depth (0 = FHP_MAX_DEPTH), target band height (0 = 32) and workgroup size
+ * (0 = smallest that holds the widest row) of the pool's launches; only while
+ * the pool is empty. */
+int fhp_pool_set_tiling(fhp_pool *pl, uint32_t depth, uint32_t band, uint32_t group_threads);
+
+/* Admits a job: creates the lattice of *p at t = 0 in the arena and schedules
+ * `steps` steps.  FHP_E_BUSY when no slot, memory or band room is free (the
+ * caller keeps the job queued).  Synchronises the pool's stream. */
+int fhp_pool_admit(fhp_pool *pl, const fhp_params *p, uint64_t steps, uint32_t *slot);
+
+/* Runs up to `passes` passes (depth K each) of every resident job that has
+ * steps left, and finishes jobs whose remaining steps are fewer than K.
+ * Asynchronous. */
+int fhp_pool_tick(fhp_pool *pl, uint32_t passes);
+
+/* Returns (and forgets) up to cap slots whose jobs have had all their steps
+ * enqueued since the last call. */
+int fhp_pool_done(fhp_pool *pl, uint32_t *slots, uint32_t cap, uint32_t *n_done);
+
+/* Block sums (FHP_OBS_BLOCKS layout) of a job's current state; synchronises. */
+int fhp_pool_result(fhp_pool *pl, uint32_t slot, uint32_t block, int32_t *host_dst, size_t bytes);
+
+/* Handle of the job in `slot` (observables, state access), owned by the pool. */
+int fhp_pool_member(fhp_pool *pl, uint32_t slot, fhp_sim **view);
+
+/* Frees the slot and its arena memory (waits for the pool's queued work). */
+int fhp_pool_release(fhp_pool *pl, uint32_t slot);
+
+/* Resident jobs and arena bytes in use / free. */
+int fhp_pool_usage(const fhp_pool *pl, uint32_t *active, size_t *bytes_used, size_t *bytes_free);
+
+/* Waits for the pool's work; FHP_E_DEVICE if a launch aborted. */
+int fhp_pool_sync(fhp_pool *pl);
+
+/* Releases the pool (not the arena). */
+void fhp_pool_destroy(fhp_pool *pl);
+
 #ifdef __cplusplus
 }
 #endif

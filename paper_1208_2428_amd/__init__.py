@@ -7,7 +7,7 @@ and fails loudly when it has not been built.
 from ._binding import (CHIR_HASH, CHIR_ONE, CHIR_ZERO, MAX_DEPTH, FhpError,  # noqa: F401
                        load)
 
-__all__ = ["Sim", "Batch", "FhpError", "CHIR_HASH", "CHIR_ZERO", "CHIR_ONE", "MAX_DEPTH", "load"]
+__all__ = ["Sim", "Batch", "Pool", "FhpError", "CHIR_HASH", "CHIR_ZERO", "CHIR_ONE", "MAX_DEPTH", "load"]
 
 
 def __getattr__(name):
@@ -17,4 +17,7 @@ def __getattr__(name):
     if name == "Batch":
         from .batch import Batch
         return Batch
+    if name == "Pool":
+        from .pool import Pool
+        return Pool
     raise AttributeError(name)

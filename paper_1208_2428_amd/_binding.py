@@ -77,6 +77,28 @@ _SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_void_p)]),
     "fhp_batch_sync": (ctypes.c_int, [ctypes.c_void_p]),
     "fhp_batch_destroy": (None, [ctypes.c_void_p]),
+    "fhp_pool_workspace_bytes": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_size_t,
+                                                ctypes.POINTER(ctypes.c_size_t)]),
+    "fhp_pool_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint32,
+                                       ctypes.c_uint32, ctypes.c_void_p,
+                                       ctypes.POINTER(ctypes.c_void_p)]),
+    "fhp_pool_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                           ctypes.c_uint32]),
+    "fhp_pool_admit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_uint64,
+                                      ctypes.POINTER(ctypes.c_uint32)]),
+    "fhp_pool_tick": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "fhp_pool_done": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
+                                     ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]),
+    "fhp_pool_result": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                       ctypes.c_void_p, ctypes.c_size_t]),
+    "fhp_pool_member": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32,
+                                       ctypes.POINTER(ctypes.c_void_p)]),
+    "fhp_pool_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "fhp_pool_usage": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
+                                      ctypes.POINTER(ctypes.c_size_t),
+                                      ctypes.POINTER(ctypes.c_size_t)]),
+    "fhp_pool_sync": (ctypes.c_int, [ctypes.c_void_p]),
+    "fhp_pool_destroy": (None, [ctypes.c_void_p]),
 }
 
 

@@ -24,6 +24,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <new>
+#include <utility>
 #include <vector>
 
 #include "fhp_device.h"
@@ -329,40 +331,360 @@ uint32_t band_for(uint32_t H, uint32_t target, uint32_t K) {
 }  // namespace
 }  // namespace fhp
 
+// ---------------------------------------------------------------------------
+// Host side.  An Engine owns the device tables of one set of lattices and
+// launches the batch kernel over them; batches (fixed members) and pools
+// (members that come and go) both drive an Engine.
+
+namespace fhp {
+namespace {
+
+struct Engine {
+    hipStream_t st = nullptr;
+    BatchHeader* hdr = nullptr;
+    MemberDesc* members = nullptr;
+    GroupDesc* groups = nullptr;
+    uint32_t* seg_member = nullptr;
+    uint32_t* seg_band = nullptr;
+    uint32_t* done = nullptr;
+    uint32_t max_members = 0, max_segs = 0;
+    // tiling
+    uint32_t depth = FHP_MAX_DEPTH, band = 32, nt_req = 0, passes_per_launch = 1;
+    int use_graph = 1;
+    // current tables
+    uint32_t nt = 64, n_groups = 0, n_done = 0, n_members = 0;
+    bool force = false, mask = false;
+    // pinned staging for the table uploads, reusable once `staged` completed
+    uint8_t* stage = nullptr;
+    size_t stage_bytes = 0;
+    hipEvent_t staged = nullptr;
+    // graph of the last launch sequence
+    hipGraphExec_t graph = nullptr;
+    uint32_t g_K = 0, g_passes = 0, g_launches = 0, g_nt = 0, g_grid = 0;
+    bool g_force = false, g_mask = false;
+};
+
+// Device table space for up to `members` lattices and `segs` bands.
+size_t engine_table_words(uint32_t members, uint32_t segs) {
+    const size_t w = sizeof(uint64_t);
+    return round_up(sizeof(BatchHeader), 256) / w + round_up((size_t)members * sizeof(MemberDesc), 256) / w +
+           round_up((size_t)segs * sizeof(GroupDesc), 256) / w + 3 * (round_up((size_t)segs * 4, 256) / w);
+}
+
+int engine_init(Engine* e, uint64_t* tables, uint32_t members, uint32_t segs, hipStream_t st) {
+    const size_t w = sizeof(uint64_t);
+    uint64_t* p = tables;
+    e->hdr = (BatchHeader*)p;
+    p += round_up(sizeof(BatchHeader), 256) / w;
+    e->members = (MemberDesc*)p;
+    p += round_up((size_t)members * sizeof(MemberDesc), 256) / w;
+    e->groups = (GroupDesc*)p;
+    p += round_up((size_t)segs * sizeof(GroupDesc), 256) / w;
+    e->seg_member = (uint32_t*)p;
+    p += round_up((size_t)segs * 4, 256) / w;
+    e->seg_band = (uint32_t*)p;
+    p += round_up((size_t)segs * 4, 256) / w;
+    e->done = (uint32_t*)p;
+    e->max_members = members;
+    e->max_segs = segs;
+    e->st = st;
+    e->stage_bytes = sizeof(BatchHeader) + (size_t)members * sizeof(MemberDesc) +
+                     (size_t)segs * (sizeof(GroupDesc) + 8);
+    FHP_HIP_TRY(hipHostMalloc((void**)&e->stage, e->stage_bytes, hipHostMallocDefault), "pinned");
+    FHP_HIP_TRY(hipEventCreateWithFlags(&e->staged, hipEventDisableTiming), "event");
+    FHP_HIP_TRY(launch_fill_u64((uint64_t*)e->done, (segs + 1) / 2, 0, st), "clear");
+    return FHP_OK;
+}
+
+void engine_free(Engine* e) {
+    if (e->graph) (void)hipGraphExecDestroy(e->graph);
+    if (e->staged) (void)hipEventDestroy(e->staged);
+    if (e->stage) (void)hipHostFree(e->stage);
+    e->graph = nullptr;
+    e->staged = nullptr;
+    e->stage = nullptr;
+}
+
+MemberDesc member_desc(const fhp_sim* s, uint32_t passes, uint32_t T, uint32_t done_off) {
+    MemberDesc M;
+    memset(&M, 0, sizeof(M));
+    M.buf[0] = s->buf[0];
+    M.buf[1] = s->buf[1];
+    M.S = s->has_mask ? s->S : nullptr;
+    M.ps = s->L.ps;
+    M.t0 = s->t;
+    M.key_chir = s->D.key_chir;
+    M.key_force = s->D.key_force;
+    M.thr_force = s->D.thr_force;
+    M.chi_and = (s->D.chir_mode == FHP_CHIR_HASH) ? ~0ull : 0ull;
+    M.chi_or = (s->D.chir_mode == FHP_CHIR_ONE) ? ~0ull : 0ull;
+    M.H = s->L.H;
+    M.wd = s->L.wd;
+    M.walls = s->L.walls;
+    M.cur = (uint32_t)s->cur;
+    M.passes = passes;
+    M.T = T;
+    M.nbands = s->L.H / T;
+    M.done_off = done_off;
+    return M;
+}
+
+// Builds the member and group tables of sims[0..n) (pass limits `limit`, or
+// no limit) and enqueues their upload on the engine's stream.
+int engine_build(Engine* e, fhp_sim* const* sims, const uint32_t* limit, uint32_t n) {
+    if (n > e->max_members) return fail(FHP_E_NOMEM, "%u lattices, room for %u", n, e->max_members);
+    struct Seg {
+        uint32_t wd, T, H, m, band;
+    };
+    std::vector<MemberDesc> mem(n);
+    std::vector<Seg> segs;
+    uint32_t done = 0, max_wd = 0;
+    bool force = false, mask = false;
+    for (uint32_t i = 0; i < n; i++) {
+        const fhp_sim* s = sims[i];
+        const uint32_t T = band_for(s->L.H, e->band, e->depth);
+        mem[i] = member_desc(s, limit ? limit[i] : kNoLimit, T, done);
+        done += mem[i].nbands;
+        for (uint32_t k = 0; k < mem[i].nbands; k++) segs.push_back({s->L.wd, T, s->L.H, i, k});
+        if (s->L.wd > max_wd) max_wd = s->L.wd;
+        force |= s->D.thr_force != 0;
+        mask |= s->has_mask != 0;
+    }
+    if (segs.size() > e->max_segs)
+        return fail(FHP_E_NOMEM, "%zu bands, room for %u", segs.size(), e->max_segs);
+    uint32_t nt = e->nt_req ? e->nt_req : 64;
+    const uint32_t need = (max_wd + 63) / 64 * 64;
+    if (nt < need) nt = need;
+    // bands of equal (wd, T) share a workgroup; larger work first
+    std::stable_sort(segs.begin(), segs.end(), [](const Seg& x, const Seg& y) {
+        if (x.wd != y.wd) return x.wd > y.wd;
+        return x.T > y.T;
+    });
+    std::vector<GroupDesc> groups;
+    std::vector<uint32_t> sm(segs.size()), sb(segs.size());
+    for (size_t k = 0; k < segs.size();) {
+        GroupDesc g;
+        g.first = (uint32_t)k;
+        g.wd = segs[k].wd;
+        g.T = segs[k].T;
+        g.nseg = 0;
+        const uint32_t cap = nt / g.wd;
+        while (k < segs.size() && g.nseg < cap && segs[k].wd == g.wd && segs[k].T == g.T) {
+            sm[k] = segs[k].m;
+            sb[k] = segs[k].band;
+            g.nseg++;
+            k++;
+        }
+        groups.push_back(g);
+    }
+    std::stable_sort(groups.begin(), groups.end(), [](const GroupDesc& x, const GroupDesc& y) {
+        return (uint64_t)x.nseg * x.wd * x.T > (uint64_t)y.nseg * y.wd * y.T;
+    });
+    BatchHeader h;
+    memset(&h, 0, sizeof(h));
+    h.n_groups = (uint32_t)groups.size();
+    h.n_members = n;
+    h.n_done = done;
+    // stage into pinned memory (after the previous upload has been consumed)
+    FHP_HIP_TRY(hipEventSynchronize(e->staged), "event");
+    uint8_t* p = e->stage;
+    const size_t bh = sizeof(h), bm = mem.size() * sizeof(MemberDesc),
+                 bg = groups.size() * sizeof(GroupDesc), bs = segs.size() * 4;
+    memcpy(p, &h, bh);
+    memcpy(p + bh, mem.data(), bm);
+    memcpy(p + bh + bm, groups.data(), bg);
+    memcpy(p + bh + bm + bg, sm.data(), bs);
+    memcpy(p + bh + bm + bg + bs, sb.data(), bs);
+    FHP_HIP_TRY(hipMemcpyAsync(e->hdr, p, bh, hipMemcpyHostToDevice, e->st), "upload");
+    if (bm) FHP_HIP_TRY(hipMemcpyAsync(e->members, p + bh, bm, hipMemcpyHostToDevice, e->st), "upload");
+    if (bg) FHP_HIP_TRY(hipMemcpyAsync(e->groups, p + bh + bm, bg, hipMemcpyHostToDevice, e->st), "upload");
+    if (bs) {
+        FHP_HIP_TRY(hipMemcpyAsync(e->seg_member, p + bh + bm + bg, bs, hipMemcpyHostToDevice, e->st), "upload");
+        FHP_HIP_TRY(hipMemcpyAsync(e->seg_band, p + bh + bm + bg + bs, bs, hipMemcpyHostToDevice, e->st), "upload");
+    }
+    FHP_HIP_TRY(hipEventRecord(e->staged, e->st), "event");
+    if (done > e->n_done)  // counters beyond the previous tables may be stale
+        FHP_HIP_TRY(launch_fill_u64((uint64_t*)e->done, (done + 1) / 2, 0, e->st), "clear");
+    e->nt = nt;
+    e->n_groups = h.n_groups;
+    e->n_done = done;
+    e->n_members = n;
+    e->force = force;
+    e->mask = mask;
+    return FHP_OK;
+}
+
+int engine_kernel(Engine* e, uint32_t K, BatchLaunch* fn, uint32_t* grid) {
+    BatchKernel kern;
+    if (!pick_kernel(K, e->force, e->mask, fn, &kern)) return fail(FHP_E_INVAL, "depth %u", K);
+    int per_cu = 0, dev = 0, cus = 0;
+    FHP_HIP_TRY(hipGetDevice(&dev), "device");
+    FHP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "attr");
+    FHP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)e->nt,
+                                                            (2 * e->nt + 1) * sizeof(uint32_t)),
+                "occupancy");
+    *grid = (uint32_t)((per_cu < 1 ? 1 : per_cu) * cus);
+    return FHP_OK;
+}
+
+int engine_enqueue(Engine* e, uint32_t K, uint32_t passes, uint32_t launches) {
+    BatchLaunch fn;
+    uint32_t grid;
+    int rc = engine_kernel(e, K, &fn, &grid);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_batch_header, dim3(1), dim3(1), 0, e->st, e->hdr, passes, K);
+    FHP_HIP_TRY(hipGetLastError(), "launch");
+    for (uint32_t k = 0; k < launches; k++)
+        FHP_HIP_TRY(fn(e->hdr, e->members, e->groups, e->seg_member, e->seg_band, e->done, grid,
+                       e->nt, e->st), "launch");
+    return FHP_OK;
+}
+
+// `launches` launches of `passes` passes of depth K, replayed from a graph
+// when enabled (the tables are read from device memory, so a graph stays valid
+// while the number of groups and members changes).
+int engine_run(Engine* e, uint32_t K, uint32_t passes, uint32_t launches) {
+    if (!e->use_graph) return engine_enqueue(e, K, passes, launches);
+    BatchLaunch fn;
+    uint32_t grid;
+    int rc = engine_kernel(e, K, &fn, &grid);
+    if (rc) return rc;
+    if (!e->graph || e->g_K != K || e->g_passes != passes || e->g_launches != launches ||
+        e->g_nt != e->nt || e->g_grid != grid || e->g_force != e->force || e->g_mask != e->mask) {
+        if (e->graph) {
+            (void)hipGraphExecDestroy(e->graph);
+            e->graph = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        FHP_HIP_TRY(hipStreamBeginCapture(e->st, hipStreamCaptureModeThreadLocal), "capture");
+        rc = engine_enqueue(e, K, passes, launches);
+        hipError_t err = hipStreamEndCapture(e->st, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (err != hipSuccess) return hip_fail(err, "end capture");
+        err = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (err != hipSuccess) {
+            e->graph = nullptr;
+            return hip_fail(err, "instantiate");
+        }
+        e->g_K = K;
+        e->g_passes = passes;
+        e->g_launches = launches;
+        e->g_nt = e->nt;
+        e->g_grid = grid;
+        e->g_force = e->force;
+        e->g_mask = e->mask;
+    }
+    FHP_HIP_TRY(hipGraphLaunch(e->graph, e->st), "graph launch");
+    return FHP_OK;
+}
+
+int engine_status(Engine* e) {
+    FHP_HIP_TRY(hipStreamSynchronize(e->st), "sync");
+    uint32_t status = 0;
+    FHP_HIP_TRY(hipMemcpy(&status, &e->hdr->status, 4, hipMemcpyDeviceToHost), "copy");
+    if (status) return fail(FHP_E_DEVICE, "batch launch aborted: a dependency wait timed out");
+    return FHP_OK;
+}
+
+// Advances lattices whose tables are current by n steps: full passes through
+// the engine, the remainder of n mod K as one more pass of that depth.
+int engine_steps(Engine* e, uint64_t n) {
+    const uint32_t K = e->depth;
+    const uint64_t full = n / K;
+    const uint32_t rest = (uint32_t)(n % K);
+    if (full) {
+        uint32_t per = e->passes_per_launch ? e->passes_per_launch : (uint32_t)full;
+        if (per > full) per = (uint32_t)full;
+        const uint32_t launches = (uint32_t)(full / per), tail = (uint32_t)(full % per);
+        int rc = engine_run(e, K, per, launches);
+        if (rc) return rc;
+        if (tail) {
+            rc = engine_enqueue(e, K, tail, 1);
+            if (rc) return rc;
+        }
+    }
+    if (rest) return engine_enqueue(e, rest, 1, 1);
+    return FHP_OK;
+}
+
+// First-fit allocator of 256-byte blocks over the pool's lattice heap.
+struct Heap {
+    std::vector<std::pair<size_t, size_t>> free_list;  // (offset, size) in words, sorted
+    size_t alloc(size_t words) {
+        for (size_t i = 0; i < free_list.size(); i++) {
+            if (free_list[i].second >= words) {
+                const size_t off = free_list[i].first;
+                free_list[i].first += words;
+                free_list[i].second -= words;
+                if (!free_list[i].second) free_list.erase(free_list.begin() + i);
+                return off;
+            }
+        }
+        return SIZE_MAX;
+    }
+    void release(size_t off, size_t words) {
+        auto it = std::lower_bound(free_list.begin(), free_list.end(), std::make_pair(off, (size_t)0));
+        it = free_list.insert(it, {off, words});
+        if (it + 1 != free_list.end() && it->first + it->second == (it + 1)->first) {
+            it->second += (it + 1)->second;
+            free_list.erase(it + 1);
+        }
+        if (it != free_list.begin() && (it - 1)->first + (it - 1)->second == it->first) {
+            (it - 1)->second += it->second;
+            free_list.erase(it);
+        }
+    }
+    size_t free_words() const {
+        size_t s = 0;
+        for (auto& f : free_list) s += f.second;
+        return s;
+    }
+};
+
+}  // namespace
+}  // namespace fhp
+
 using namespace fhp;
 
 struct fhp_batch {
     uint32_t n;
     fhp_sim* sims;
-    hipStream_t st;
-    // device tables
-    BatchHeader* hdr;
-    MemberDesc* members;
-    GroupDesc* groups;
-    uint32_t* seg_member;
-    uint32_t* seg_band;
-    uint32_t* done;
+    std::vector<fhp_sim*> ptrs;
     uint64_t* aux;
-    size_t max_segs;
-    // tiling
-    uint32_t depth, band, nt, passes_per_launch;
-    int use_graph;
-    bool force, mask;
-    bool tables_dirty;  // member table or grouping must be uploaded before the next launch
-    int dirty_flag;     // set by member views when they are changed individually
-    uint32_t n_groups, n_done;
-    uint32_t grid;      // persistent workgroups of the current kernel
-    // cached graph of one launch sequence
-    hipGraphExec_t graph;
-    uint32_t graph_K, graph_passes, graph_launches;
+    Engine eng;
+    bool tables_dirty;  // tiling changed: rebuild before the next step
+    int changed;        // set by member handles when a member is changed alone
+};
+
+// One job of a pool.
+struct PoolSlot {
+    bool used = false;
+    fhp_sim sim;
+    size_t heap_off = 0, heap_words = 0;
+    uint64_t remaining = 0;  // steps still to run
+};
+
+struct fhp_pool {
+    Engine eng;
+    uint64_t* heap_base;
+    Heap heap;
+    size_t heap_words;
+    uint64_t* aux;
+    std::vector<PoolSlot> slots;
+    std::vector<uint32_t> finished;  // done slots not yet reported
+    uint32_t max_bands, bands_used;
+    int changed;
 };
 
 namespace {
 
 struct BatchLayout {
     std::vector<size_t> member_off;  // word offsets of each member's planes
-    size_t aux_off, hdr_off, members_off, groups_off, segm_off, segb_off, done_off;
-    size_t max_segs, total_bytes;
+    size_t aux_off, tables_off, max_segs, total_bytes;
 };
 
 int batch_layout(const fhp_params* ps, uint32_t n, BatchLayout* bl) {
@@ -379,187 +701,42 @@ int batch_layout(const fhp_params* ps, uint32_t n, BatchLayout* bl) {
             return fail(FHP_E_INVAL, "member %u: height %u below %u", i, ps[i].height,
                         2 * FHP_MAX_DEPTH);
         bl->member_off[i] = off;
-        off += layout_for(ps[i].width, ps[i].height).aux_off;  // planes and S, no aux
-        off = round_up(off, 32);
+        off += round_up(layout_for(ps[i].width, ps[i].height).aux_off, 32);  // planes and S
         segs += ps[i].height / 2;  // bands of at least 2 rows
     }
     bl->aux_off = off;
     off += kAuxWords;
-    const size_t w = sizeof(uint64_t);
-    bl->hdr_off = off;
-    off += round_up(sizeof(BatchHeader), 256) / w;
-    bl->members_off = off;
-    off += round_up((size_t)n * sizeof(MemberDesc), 256) / w;
-    bl->groups_off = off;
-    off += round_up(segs * sizeof(GroupDesc), 256) / w;
-    bl->segm_off = off;
-    off += round_up(segs * 4, 256) / w;
-    bl->segb_off = off;
-    off += round_up(segs * 4, 256) / w;
-    bl->done_off = off;
-    off += round_up(segs * 4, 256) / w;
+    bl->tables_off = off;
+    off += engine_table_words(n, (uint32_t)segs);
     bl->max_segs = segs;
-    bl->total_bytes = off * w;
+    bl->total_bytes = off * sizeof(uint64_t);
     return FHP_OK;
 }
 
-// Rebuilds the member and group tables for the current tiling and uploads them.
-int build_tables(fhp_batch* b) {
-    FHP_HIP_TRY(hipStreamSynchronize(b->st), "sync");
-    std::vector<MemberDesc> mem(b->n);
-    struct Seg {
-        uint32_t wd, T, m, band;
-    };
-    std::vector<Seg> segs;
-    uint32_t done = 0, max_wd = 0;
-    for (uint32_t i = 0; i < b->n; i++) {
-        const fhp_sim* s = &b->sims[i];
-        MemberDesc& M = mem[i];
-        memset(&M, 0, sizeof(M));
-        M.buf[0] = s->buf[0];
-        M.buf[1] = s->buf[1];
-        M.S = s->has_mask ? s->S : nullptr;
-        M.ps = s->L.ps;
-        M.t0 = s->t;
-        M.key_chir = s->D.key_chir;
-        M.key_force = s->D.key_force;
-        M.thr_force = s->D.thr_force;
-        M.chi_and = (s->D.chir_mode == FHP_CHIR_HASH) ? ~0ull : 0ull;
-        M.chi_or = (s->D.chir_mode == FHP_CHIR_ONE) ? ~0ull : 0ull;
-        M.H = s->L.H;
-        M.wd = s->L.wd;
-        M.walls = s->L.walls;
-        M.cur = (uint32_t)s->cur;
-        M.passes = kNoLimit;
-        M.T = band_for(s->L.H, b->band, b->depth);
-        M.nbands = s->L.H / M.T;
-        M.done_off = done;
-        done += M.nbands;
-        for (uint32_t k = 0; k < M.nbands; k++) segs.push_back({M.wd, M.T, i, k});
-        if (M.wd > max_wd) max_wd = M.wd;
-    }
-    uint32_t nt = b->nt ? b->nt : 64;
-    const uint32_t need = (max_wd + 63) / 64 * 64;
-    if (nt < need) nt = need;
-    // group bands of equal (wd, T); larger work first
-    std::stable_sort(segs.begin(), segs.end(), [](const Seg& x, const Seg& y) {
-        if (x.wd != y.wd) return x.wd > y.wd;
-        return x.T > y.T;
-    });
-    std::vector<GroupDesc> groups;
-    std::vector<uint32_t> sm(segs.size()), sb(segs.size());
-    for (size_t k = 0; k < segs.size();) {
-        const uint32_t cap = nt / segs[k].wd;
-        GroupDesc g;
-        g.first = (uint32_t)k;
-        g.wd = segs[k].wd;
-        g.T = segs[k].T;
-        g.nseg = 0;
-        while (k < segs.size() && g.nseg < cap && segs[k].wd == g.wd && segs[k].T == g.T) {
-            sm[k] = segs[k].m;
-            sb[k] = segs[k].band;
-            g.nseg++;
-            k++;
-        }
-        groups.push_back(g);
-    }
-    std::stable_sort(groups.begin(), groups.end(), [](const GroupDesc& x, const GroupDesc& y) {
-        return (uint64_t)x.nseg * x.wd * x.T > (uint64_t)y.nseg * y.wd * y.T;
-    });
-    BatchHeader h;
-    memset(&h, 0, sizeof(h));
-    h.n_groups = (uint32_t)groups.size();
-    h.n_members = b->n;
-    h.n_done = done;
-    FHP_HIP_TRY(hipMemcpy(b->hdr, &h, sizeof(h), hipMemcpyHostToDevice), "upload");
-    FHP_HIP_TRY(hipMemcpy(b->members, mem.data(), mem.size() * sizeof(MemberDesc),
-                          hipMemcpyHostToDevice), "upload");
-    FHP_HIP_TRY(hipMemcpy(b->groups, groups.data(), groups.size() * sizeof(GroupDesc),
-                          hipMemcpyHostToDevice), "upload");
-    FHP_HIP_TRY(hipMemcpy(b->seg_member, sm.data(), sm.size() * 4, hipMemcpyHostToDevice), "upload");
-    FHP_HIP_TRY(hipMemcpy(b->seg_band, sb.data(), sb.size() * 4, hipMemcpyHostToDevice), "upload");
-    FHP_HIP_TRY(launch_fill_u64((uint64_t*)b->done, (done + 1) / 2, 0, b->st), "clear");
-    FHP_HIP_TRY(hipStreamSynchronize(b->st), "sync");
-    b->nt = nt;
-    b->n_groups = h.n_groups;
-    b->n_done = done;
-    b->force = b->mask = false;
-    for (uint32_t i = 0; i < b->n; i++) {
-        b->force |= b->sims[i].D.thr_force != 0;
-        b->mask |= b->sims[i].has_mask != 0;
-    }
-    b->tables_dirty = false;
-    b->dirty_flag = 0;
-    if (b->graph) {
-        (void)hipGraphExecDestroy(b->graph);
-        b->graph = nullptr;
-    }
-    return FHP_OK;
-}
-
-int kernel_for(fhp_batch* b, uint32_t K, BatchLaunch* fn) {
-    BatchKernel kern;
-    if (!pick_kernel(K, b->force, b->mask, fn, &kern)) return fail(FHP_E_INVAL, "depth %u", K);
-    int per_cu = 0, dev = 0, cus = 0;
-    FHP_HIP_TRY(hipGetDevice(&dev), "device");
-    FHP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "attr");
-    FHP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)b->nt,
-                                                            (2 * b->nt + 1) * sizeof(uint32_t)),
-                "occupancy");
-    if (per_cu < 1) per_cu = 1;
-    b->grid = (uint32_t)(per_cu * cus);
-    return FHP_OK;
-}
-
-// Enqueues `launches` launches of `passes` passes of depth K.
-int enqueue(fhp_batch* b, uint32_t K, uint32_t passes, uint32_t launches) {
-    BatchLaunch fn;
-    int rc = kernel_for(b, K, &fn);
+int batch_rebuild(fhp_batch* b) {
+    int rc = engine_build(&b->eng, b->ptrs.data(), nullptr, b->n);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_batch_header, dim3(1), dim3(1), 0, b->st, b->hdr, passes, K);
-    FHP_HIP_TRY(hipGetLastError(), "launch");
-    for (uint32_t k = 0; k < launches; k++)
-        FHP_HIP_TRY(fn(b->hdr, b->members, b->groups, b->seg_member, b->seg_band, b->done,
-                       b->grid, b->nt, b->st), "launch");
+    b->tables_dirty = false;
+    b->changed = 0;
     return FHP_OK;
 }
 
-int launch_graphless(fhp_batch* b, uint32_t K, uint32_t passes, uint32_t launches) {
-    return enqueue(b, K, passes, launches);
-}
-
-int launch_graph(fhp_batch* b, uint32_t K, uint32_t passes, uint32_t launches) {
-    if (!b->graph || b->graph_K != K || b->graph_passes != passes || b->graph_launches != launches) {
-        if (b->graph) {
-            (void)hipGraphExecDestroy(b->graph);
-            b->graph = nullptr;
-        }
-        hipGraph_t g = nullptr;
-        FHP_HIP_TRY(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal), "capture");
-        int rc = enqueue(b, K, passes, launches);
-        hipError_t e = hipStreamEndCapture(b->st, &g);
-        if (rc) {
-            if (g) (void)hipGraphDestroy(g);
-            return rc;
-        }
-        if (e != hipSuccess) return hip_fail(e, "end capture");
-        e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (e != hipSuccess) {
-            b->graph = nullptr;
-            return hip_fail(e, "instantiate");
-        }
-        b->graph_K = K;
-        b->graph_passes = passes;
-        b->graph_launches = launches;
-    }
-    FHP_HIP_TRY(hipGraphLaunch(b->graph, b->st), "graph launch");
+// Pool member validation: the batch kernel's limits plus the pool's band room.
+int pool_check(const fhp_params* p) {
+    int rc = validate(p);
+    if (rc) return rc;
+    if (p->width / 64 > kMaxBlockedWords)
+        return fail(FHP_E_INVAL, "width %u above %u", p->width, 64 * kMaxBlockedWords);
+    if (p->height < 2 * FHP_MAX_DEPTH)
+        return fail(FHP_E_INVAL, "height %u below %u", p->height, 2 * FHP_MAX_DEPTH);
     return FHP_OK;
 }
 
 }  // namespace
 
 extern "C" {
+
+// ------------------------------------------------------------------ batches
 
 int fhp_batch_workspace_bytes(const fhp_params* ps, uint32_t n, size_t* bytes) {
     if (!bytes) return fail(FHP_E_INVAL, "bytes is NULL");
@@ -581,39 +758,30 @@ int fhp_batch_create(const fhp_params* ps, uint32_t n, void* dev_ws, size_t ws_b
         return fail(FHP_E_INVAL, "workspace must be a non-NULL 256-byte aligned device pointer");
     if (ws_bytes < bl.total_bytes)
         return fail(FHP_E_NOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, bl.total_bytes);
-    fhp_batch* b = (fhp_batch*)calloc(1, sizeof(fhp_batch));
+    fhp_batch* b = new (std::nothrow) fhp_batch();
     if (!b) return fail(FHP_E_NOMEM, "host allocation failed");
     b->sims = (fhp_sim*)calloc(n, sizeof(fhp_sim));
     if (!b->sims) {
-        free(b);
+        delete b;
         return fail(FHP_E_NOMEM, "host allocation failed");
     }
     uint64_t* ws = (uint64_t*)dev_ws;
+    hipStream_t st = (hipStream_t)hip_stream;
     b->n = n;
-    b->st = (hipStream_t)hip_stream;
     b->aux = ws + bl.aux_off;
-    b->hdr = (BatchHeader*)(ws + bl.hdr_off);
-    b->members = (MemberDesc*)(ws + bl.members_off);
-    b->groups = (GroupDesc*)(ws + bl.groups_off);
-    b->seg_member = (uint32_t*)(ws + bl.segm_off);
-    b->seg_band = (uint32_t*)(ws + bl.segb_off);
-    b->done = (uint32_t*)(ws + bl.done_off);
-    b->max_segs = bl.max_segs;
-    b->depth = FHP_MAX_DEPTH;
-    b->band = 32;
-    b->nt = 0;
-    b->passes_per_launch = 1;
-    b->use_graph = 1;
+    rc = engine_init(&b->eng, ws + bl.tables_off, n, (uint32_t)bl.max_segs, st);
     for (uint32_t i = 0; i < n && !rc; i++) {
         const Layout lay = layout_for(ps[i].width, ps[i].height);
-        rc = sim_setup(&b->sims[i], &ps[i], ws + bl.member_off[i], lay, b->aux, b->st);
+        rc = sim_setup(&b->sims[i], &ps[i], ws + bl.member_off[i], lay, b->aux, st);
         b->sims[i].owner = b;
-        b->sims[i].changed = &b->dirty_flag;
+        b->sims[i].changed = &b->changed;
+        b->ptrs.push_back(&b->sims[i]);
     }
-    if (!rc) rc = build_tables(b);
+    if (!rc) rc = batch_rebuild(b);
     if (rc) {
+        engine_free(&b->eng);
         free(b->sims);
-        free(b);
+        delete b;
         return rc;
     }
     *out = b;
@@ -626,16 +794,16 @@ int fhp_batch_set_tiling(fhp_batch* b, uint32_t depth, uint32_t band, uint32_t g
     if (depth > FHP_MAX_DEPTH) return fail(FHP_E_INVAL, "depth %u above %u", depth, FHP_MAX_DEPTH);
     if (group_threads % 64 || group_threads > 512)
         return fail(FHP_E_INVAL, "group_threads %u: a multiple of 64 up to 512", group_threads);
-    b->depth = depth ? depth : FHP_MAX_DEPTH;
-    b->band = band ? band : 32;
-    b->nt = group_threads;
-    b->passes_per_launch = passes_per_launch;  // 0: all passes of a call in one launch
-    return build_tables(b);
+    b->eng.depth = depth ? depth : FHP_MAX_DEPTH;
+    b->eng.band = band ? band : 32;
+    b->eng.nt_req = group_threads;
+    b->eng.passes_per_launch = passes_per_launch;
+    return batch_rebuild(b);
 }
 
 int fhp_batch_set_graph(fhp_batch* b, int enable) {
     if (!b) return fail(FHP_E_INVAL, "batch is NULL");
-    b->use_graph = enable != 0;
+    b->eng.use_graph = enable != 0;
     return FHP_OK;
 }
 
@@ -644,35 +812,18 @@ int fhp_batch_step(fhp_batch* b, uint64_t n) {
     for (uint32_t i = 0; i < b->n; i++)
         if (b->sims[i].t + n >= kTimeLimit)
             return fail(FHP_E_STATE, "member %u: time would reach 2^24", i);
-    if (b->tables_dirty || b->dirty_flag) {
-        int rc = build_tables(b);
+    if (b->tables_dirty || b->changed) {
+        int rc = batch_rebuild(b);
         if (rc) return rc;
     }
-    const uint32_t K = b->depth;
-    const uint64_t full = n / K;
-    const uint32_t rest = (uint32_t)(n % K);
-    if (full) {
-        uint32_t per = b->passes_per_launch ? b->passes_per_launch : (uint32_t)full;
-        if (per > full) per = (uint32_t)full;
-        const uint32_t launches = (uint32_t)(full / per);
-        const uint32_t tail = (uint32_t)(full % per);
-        int rc = b->use_graph ? launch_graph(b, K, per, launches) : launch_graphless(b, K, per, launches);
-        if (rc) return rc;
-        if (tail) {
-            rc = launch_graphless(b, K, tail, 1);
-            if (rc) return rc;
-        }
-    }
-    if (rest) {
-        int rc = launch_graphless(b, rest, 1, 1);
-        if (rc) return rc;
-    }
+    int rc = engine_steps(&b->eng, n);
+    if (rc) return rc;
     // host mirror of the device-side bookkeeping
+    const uint32_t K = b->eng.depth;
+    const uint64_t passes = n / K + ((n % K) ? 1 : 0);
     for (uint32_t i = 0; i < b->n; i++) {
-        fhp_sim* s = &b->sims[i];
-        const uint64_t passes = full + (rest ? 1 : 0);
-        s->t += n;
-        s->cur ^= (int)(passes & 1);
+        b->sims[i].t += n;
+        b->sims[i].cur ^= (int)(passes & 1);
     }
     return FHP_OK;
 }
@@ -686,19 +837,222 @@ int fhp_batch_member(fhp_batch* b, uint32_t i, fhp_sim** view) {
 
 int fhp_batch_sync(fhp_batch* b) {
     if (!b) return fail(FHP_E_INVAL, "batch is NULL");
-    FHP_HIP_TRY(hipStreamSynchronize(b->st), "sync");
-    uint32_t status = 0;
-    FHP_HIP_TRY(hipMemcpy(&status, &b->hdr->status, 4, hipMemcpyDeviceToHost), "copy");
-    if (status) return fail(FHP_E_DEVICE, "batch launch aborted: a dependency wait timed out");
-    return FHP_OK;
+    return engine_status(&b->eng);
 }
 
 void fhp_batch_destroy(fhp_batch* b) {
     if (!b) return;
-    (void)hipStreamSynchronize(b->st);
-    if (b->graph) (void)hipGraphExecDestroy(b->graph);
+    (void)hipStreamSynchronize(b->eng.st);
+    engine_free(&b->eng);
     free(b->sims);
-    free(b);
+    delete b;
+}
+
+// -------------------------------------------------------------------- pools
+
+int fhp_pool_workspace_bytes(uint32_t max_slots, uint32_t max_bands, size_t lattice_bytes,
+                             size_t* bytes) {
+    if (!bytes || !max_slots || !max_bands) return fail(FHP_E_INVAL, "bad pool size");
+    *bytes = (kAuxWords + engine_table_words(max_slots, max_bands)) * sizeof(uint64_t) +
+             round_up(lattice_bytes, 256);
+    return FHP_OK;
+}
+
+int fhp_pool_create(void* dev_arena, size_t arena_bytes, uint32_t max_slots, uint32_t max_bands,
+                    void* hip_stream, fhp_pool** out) {
+    if (!out) return fail(FHP_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (!dev_arena || ((uintptr_t)dev_arena & 255))
+        return fail(FHP_E_INVAL, "arena must be a non-NULL 256-byte aligned device pointer");
+    if (!max_slots || !max_bands) return fail(FHP_E_INVAL, "bad pool size");
+    const size_t fixed = kAuxWords + engine_table_words(max_slots, max_bands);
+    if (arena_bytes / sizeof(uint64_t) <= fixed)
+        return fail(FHP_E_NOMEM, "arena of %zu bytes holds only the tables", arena_bytes);
+    fhp_pool* pl = new (std::nothrow) fhp_pool();
+    if (!pl) return fail(FHP_E_NOMEM, "host allocation failed");
+    uint64_t* a = (uint64_t*)dev_arena;
+    pl->aux = a;
+    int rc = engine_init(&pl->eng, a + kAuxWords, max_slots, max_bands, (hipStream_t)hip_stream);
+    if (rc) {
+        delete pl;
+        return rc;
+    }
+    pl->heap_base = a + fixed;
+    pl->heap_words = (arena_bytes / sizeof(uint64_t) - fixed) / 32 * 32;
+    pl->heap.free_list.push_back({0, pl->heap_words});
+    pl->slots.resize(max_slots);
+    pl->max_bands = max_bands;
+    pl->bands_used = 0;
+    *out = pl;
+    return FHP_OK;
+}
+
+int fhp_pool_set_tiling(fhp_pool* pl, uint32_t depth, uint32_t band, uint32_t group_threads) {
+    if (!pl) return fail(FHP_E_INVAL, "pool is NULL");
+    if (depth > FHP_MAX_DEPTH) return fail(FHP_E_INVAL, "depth %u above %u", depth, FHP_MAX_DEPTH);
+    if (group_threads % 64 || group_threads > 512)
+        return fail(FHP_E_INVAL, "group_threads %u: a multiple of 64 up to 512", group_threads);
+    for (auto& s : pl->slots)
+        if (s.used) return fail(FHP_E_STATE, "tiling can change only while the pool is empty");
+    pl->eng.depth = depth ? depth : FHP_MAX_DEPTH;
+    pl->eng.band = band ? band : 32;
+    pl->eng.nt_req = group_threads;
+    return FHP_OK;
+}
+
+int fhp_pool_admit(fhp_pool* pl, const fhp_params* p, uint64_t steps, uint32_t* slot) {
+    if (!pl || !slot) return fail(FHP_E_INVAL, "NULL argument");
+    int rc = pool_check(p);
+    if (rc) return rc;
+    if (steps >= kTimeLimit) return fail(FHP_E_STATE, "%llu steps: time would reach 2^24",
+                                         (unsigned long long)steps);
+    uint32_t i = 0;
+    while (i < pl->slots.size() && pl->slots[i].used) i++;
+    if (i == pl->slots.size()) return fail(FHP_E_BUSY, "all %zu slots in use", pl->slots.size());
+    const uint32_t T = band_for(p->height, pl->eng.band, pl->eng.depth);
+    const uint32_t bands = p->height / T;
+    if (pl->bands_used + bands > pl->max_bands)
+        return fail(FHP_E_BUSY, "band table full (%u of %u)", pl->bands_used, pl->max_bands);
+    const Layout lay = layout_for(p->width, p->height);
+    const size_t words = round_up(lay.aux_off, 32);
+    const size_t off = pl->heap.alloc(words);
+    if (off == SIZE_MAX) return fail(FHP_E_BUSY, "arena full (%zu bytes free, %zu needed)",
+                                     pl->heap.free_words() * 8, words * 8);
+    PoolSlot& s = pl->slots[i];
+    memset(&s.sim, 0, sizeof(s.sim));
+    rc = sim_setup(&s.sim, p, pl->heap_base + off, lay, pl->aux, pl->eng.st);
+    if (rc) {
+        pl->heap.release(off, words);
+        return rc;
+    }
+    s.sim.owner = pl;
+    s.sim.changed = &pl->changed;
+    s.used = true;
+    s.heap_off = off;
+    s.heap_words = words;
+    s.remaining = steps;
+    pl->bands_used += bands;
+    if (steps == 0) pl->finished.push_back(i);
+    *slot = i;
+    return FHP_OK;
+}
+
+int fhp_pool_tick(fhp_pool* pl, uint32_t passes) {
+    if (!pl) return fail(FHP_E_INVAL, "pool is NULL");
+    if (!passes) passes = 1;
+    const uint32_t K = pl->eng.depth;
+    std::vector<fhp_sim*> act;
+    std::vector<uint32_t> lim, idx;
+    for (uint32_t i = 0; i < pl->slots.size(); i++) {
+        PoolSlot& s = pl->slots[i];
+        if (!s.used || s.remaining < K) continue;
+        const uint64_t full = s.remaining / K;
+        act.push_back(&s.sim);
+        lim.push_back((uint32_t)(full < passes ? full : passes));
+        idx.push_back(i);
+    }
+    if (!act.empty()) {
+        int rc = engine_build(&pl->eng, act.data(), lim.data(), (uint32_t)act.size());
+        if (rc) return rc;
+        rc = engine_run(&pl->eng, K, 1, passes);  // one pass per launch
+        if (rc) return rc;
+        for (size_t k = 0; k < act.size(); k++) {
+            PoolSlot& s = pl->slots[idx[k]];
+            s.sim.t += (uint64_t)lim[k] * K;
+            s.sim.cur ^= (int)(lim[k] & 1);
+            s.remaining -= (uint64_t)lim[k] * K;
+        }
+    }
+    // Jobs left with fewer than K steps finish on the single-lattice kernels;
+    // every job that reached its last step in this tick is reported once.
+    std::vector<char> ran(pl->slots.size(), 0);
+    for (uint32_t i : idx) ran[i] = 1;
+    for (uint32_t i = 0; i < pl->slots.size(); i++) {
+        PoolSlot& s = pl->slots[i];
+        if (!s.used) continue;
+        if (s.remaining == 0) {
+            if (ran[i]) pl->finished.push_back(i);
+            continue;
+        }
+        if (s.remaining >= K) continue;
+        const uint32_t r = (uint32_t)s.remaining;
+        const uint32_t depth = s.sim.depth;
+        s.sim.depth = r;
+        int* ch = s.sim.changed;
+        s.sim.changed = nullptr;
+        int rc = fhp_step(&s.sim, r);
+        s.sim.changed = ch;
+        s.sim.depth = depth;
+        if (rc) return rc;
+        s.remaining = 0;
+        pl->finished.push_back(i);
+    }
+    return FHP_OK;
+}
+
+int fhp_pool_done(fhp_pool* pl, uint32_t* slots, uint32_t cap, uint32_t* n_done) {
+    if (!pl || !n_done || (cap && !slots)) return fail(FHP_E_INVAL, "NULL argument");
+    const uint32_t n = (uint32_t)(pl->finished.size() < cap ? pl->finished.size() : cap);
+    for (uint32_t k = 0; k < n; k++) slots[k] = pl->finished[k];
+    pl->finished.erase(pl->finished.begin(), pl->finished.begin() + n);
+    *n_done = n;
+    return FHP_OK;
+}
+
+int fhp_pool_member(fhp_pool* pl, uint32_t slot, fhp_sim** view) {
+    if (!pl || !view) return fail(FHP_E_INVAL, "NULL argument");
+    if (slot >= pl->slots.size() || !pl->slots[slot].used)
+        return fail(FHP_E_INVAL, "slot %u is not in use", slot);
+    *view = &pl->slots[slot].sim;
+    return FHP_OK;
+}
+
+int fhp_pool_result(fhp_pool* pl, uint32_t slot, uint32_t block, int32_t* host_dst, size_t bytes) {
+    fhp_sim* s = nullptr;
+    int rc = fhp_pool_member(pl, slot, &s);
+    if (rc) return rc;
+    return fhp_observe(s, FHP_OBS_BLOCKS, block, host_dst, bytes);
+}
+
+int fhp_pool_release(fhp_pool* pl, uint32_t slot) {
+    if (!pl) return fail(FHP_E_INVAL, "pool is NULL");
+    if (slot >= pl->slots.size() || !pl->slots[slot].used)
+        return fail(FHP_E_INVAL, "slot %u is not in use", slot);
+    PoolSlot& s = pl->slots[slot];
+    // the memory may be reused by the next admission: wait for work on it
+    FHP_HIP_TRY(hipStreamSynchronize(pl->eng.st), "sync");
+    pl->heap.release(s.heap_off, s.heap_words);
+    pl->bands_used -= s.sim.L.H / band_for(s.sim.L.H, pl->eng.band, pl->eng.depth);
+    s.used = false;
+    for (size_t k = 0; k < pl->finished.size(); k++)
+        if (pl->finished[k] == slot) {
+            pl->finished.erase(pl->finished.begin() + k);
+            break;
+        }
+    return FHP_OK;
+}
+
+int fhp_pool_usage(const fhp_pool* pl, uint32_t* active, size_t* bytes_used, size_t* bytes_free) {
+    if (!pl) return fail(FHP_E_INVAL, "pool is NULL");
+    uint32_t n = 0;
+    for (auto& s : pl->slots) n += s.used;
+    if (active) *active = n;
+    const size_t free_b = pl->heap.free_words() * 8;
+    if (bytes_used) *bytes_used = pl->heap_words * 8 - free_b;
+    if (bytes_free) *bytes_free = free_b;
+    return FHP_OK;
+}
+
+int fhp_pool_sync(fhp_pool* pl) {
+    if (!pl) return fail(FHP_E_INVAL, "pool is NULL");
+    return engine_status(&pl->eng);
+}
+
+void fhp_pool_destroy(fhp_pool* pl) {
+    if (!pl) return;
+    (void)hipStreamSynchronize(pl->eng.st);
+    engine_free(&pl->eng);
+    delete pl;
 }
 
 }  // extern "C"
