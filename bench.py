@@ -41,6 +41,18 @@ def golden_digest(name: str, t: int):
     return None
 
 
+def recorded_traffic(name: str, depth: int):
+    """HBM bytes per launch from the rocprofv3 counters recorded under
+    profiles/ for this kernel, or None if they were taken on other kernel
+    sources or another depth."""
+    from paper_1208_2428_amd import profsum
+    path = os.path.join(ROOT, "profiles", f"k_stepk_{name}.md")
+    traffic, src = profsum.recorded_traffic(path)
+    if traffic is None or depth != 4 or src != profsum.kernel_source_hash():
+        return None
+    return traffic
+
+
 def cpu_baseline(wl, mask, seconds: float):
     """Times the CPU oracle on a bounded sample of the workload: a full-width
     band of 1024 rows of the same lattice (same mask rows, fill and forcing),
@@ -96,6 +108,33 @@ def batched_leg(args, wl, mask, depth, value):
             "one_by_one_value": one["value"], "ratio_vs_one_by_one": res["value"] / one["value"]}
 
 
+def served_leg(args, plain, depth):
+    """Continuous batching of a Poisson stream of channel-flow jobs."""
+    from paper_1208_2428_amd import serve
+    from paper_1208_2428_amd import workloads as WL
+    reqs = WL.request_stream(n=args.serve_requests, rate=200.0, seed=5)
+    offered = serve.offered_load(reqs)
+    log(f"bench: serving {len(reqs)} requests at 200/s (offered {offered:.3e} node-updates/s)")
+    srv = serve.Server(lattice_bytes=32 << 30, max_slots=512, passes_per_tick=1, depth=depth)
+    hot = srv.run(reqs, realtime=True, log=log)
+    log(f"bench: served {hot['completed']} in {hot['seconds']:.1f} s: {hot['value']:.3e} "
+        f"node-updates/s, p50 {hot['p50_ms']:.0f} ms, p99 {hot['p99_ms']:.0f} ms")
+    # a second point at about 80% of the measured capacity
+    rate80 = 200.0 * 0.8 * hot["value"] / offered
+    n80 = max(100, len(reqs) // 4)
+    reqs80 = WL.request_stream(n=n80, rate=rate80, seed=6)
+    at80 = srv.run(reqs80, realtime=True, log=log)
+    log(f"bench: at {rate80:.0f} req/s: p50 {at80['p50_ms']:.0f} ms, p99 {at80['p99_ms']:.0f} ms")
+    srv.close()
+    keys = ("requests", "completed", "seconds", "value", "p50_ms", "p99_ms", "mean_ms",
+            "max_queue", "max_resident", "ticks")
+    return {"value": hot["value"], "unit": "node-updates/s", "ratio_vs_plain": hot["value"] / plain,
+            "offered_load": offered, "rate_per_s": 200.0, "arena_bytes": 32 << 30,
+            "overloaded": {k: hot[k] for k in keys},
+            "at_80pct_capacity": dict({k: at80[k] for k in keys}, rate_per_s=rate80,
+                                      offered_load=serve.offered_load(reqs80))}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +148,8 @@ def main() -> int:
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the 512-lattice batched ensemble comparison")
     ap.add_argument("--ensemble-steps", type=int, default=500)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -166,6 +207,7 @@ def main() -> int:
     bytes_per_launch = PLANE_BITS * nodes / 8  # 14/k bits per node-step, k steps per launch
     achieved = bytes_per_launch / launch_s / 1e9
     sim.close()
+    traffic = recorded_traffic(wl.name, depth)
 
     value = nodes * args.steps / wall
     out = {
@@ -186,11 +228,13 @@ def main() -> int:
                    "solid_fraction": round(solid_frac, 5), "depth": depth, "band": args.band,
                    "parity_digest_vs_oracle": parity},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel_us": launch_s * 1e6, "bytes_per_launch": bytes_per_launch},
     }
     if not args.no_ensemble:
         out["batched"] = batched_leg(args, wl, mask, depth, value)
+    if not args.no_serve:
+        out["served"] = served_leg(args, value, depth)
     if not args.no_cpu_baseline:
         log(f"bench: timing the CPU oracle for ~{args.cpu_seconds:.0f} s")
         out["cpu_baseline"] = cpu_baseline(wl, mask, args.cpu_seconds)

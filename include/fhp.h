@@ -239,7 +239,7 @@ int fhp_pool_set_tiling(fhp_pool *pl, uint32_t depth, uint32_t band, uint32_t gr
 
 /* Admits a job: creates the lattice of *p at t = 0 in the arena and schedules
  * `steps` steps.  FHP_E_BUSY when no slot, memory or band room is free (the
- * caller keeps the job queued).  Synchronises the pool's stream. */
+ * caller keeps the job queued).  Asynchronous unless p->solid is given. */
 int fhp_pool_admit(fhp_pool *pl, const fhp_params *p, uint64_t steps, uint32_t *slot);
 
 /* Runs up to `passes` passes (depth K each) of every resident job that has
@@ -257,7 +257,8 @@ int fhp_pool_result(fhp_pool *pl, uint32_t slot, uint32_t block, int32_t *host_d
 /* Handle of the job in `slot` (observables, state access), owned by the pool. */
 int fhp_pool_member(fhp_pool *pl, uint32_t slot, fhp_sim **view);
 
-/* Frees the slot and its arena memory (waits for the pool's queued work). */
+/* Frees the slot and its arena memory.  Work already enqueued on the job runs
+ * before anything that later reuses the memory (stream order). */
 int fhp_pool_release(fhp_pool *pl, uint32_t slot);
 
 /* Resident jobs and arena bytes in use / free. */

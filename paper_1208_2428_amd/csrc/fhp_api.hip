@@ -112,7 +112,7 @@ Lattice lattice_of(const fhp_sim* s) {
 }
 
 int sim_setup(fhp_sim* s, const fhp_params* p, uint64_t* planes, const Layout& lay,
-              uint64_t* aux, hipStream_t st) {
+              uint64_t* aux, hipStream_t st, bool sync) {
     s->p = *p;
     s->p.solid = nullptr;
     s->lay = lay;
@@ -136,16 +136,17 @@ int sim_setup(fhp_sim* s, const fhp_params* p, uint64_t* planes, const Layout& l
     s->band = 0;
 
     FHP_HIP_TRY(launch_fill_u64(s->S, lay.plane_words, 0, st), "clear solid plane");
+    s->has_mask = 0;
     if (p->solid) {
         int r = upload_bytes(s, p->solid, 1);
         if (r) return r;
+        r = refresh_has_mask(s);
+        if (r) return r;
     }
-    int r = refresh_has_mask(s);
-    if (r) return r;
     const uint64_t thr_fill = (uint64_t)floor(p->fill * 4294967296.0);  // fill * 2^32
     FHP_HIP_TRY(launch_init(s->buf[0], lattice_of(s), hash64(p->seed, kTagInit), thr_fill, st),
                 "init");
-    FHP_HIP_TRY(hipStreamSynchronize(st), "sync");
+    if (sync) FHP_HIP_TRY(hipStreamSynchronize(st), "sync");
     return FHP_OK;
 }
 

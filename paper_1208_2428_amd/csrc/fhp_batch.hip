@@ -677,7 +677,8 @@ struct fhp_pool {
     std::vector<PoolSlot> slots;
     std::vector<uint32_t> finished;  // done slots not yet reported
     uint32_t max_bands, bands_used;
-    int changed;
+    int changed;         // membership or a member changed: rebuild the tables
+    std::vector<uint32_t> table_slots;  // slots in the current tables
 };
 
 namespace {
@@ -920,7 +921,7 @@ int fhp_pool_admit(fhp_pool* pl, const fhp_params* p, uint64_t steps, uint32_t* 
                                      pl->heap.free_words() * 8, words * 8);
     PoolSlot& s = pl->slots[i];
     memset(&s.sim, 0, sizeof(s.sim));
-    rc = sim_setup(&s.sim, p, pl->heap_base + off, lay, pl->aux, pl->eng.st);
+    rc = sim_setup(&s.sim, p, pl->heap_base + off, lay, pl->aux, pl->eng.st, false);
     if (rc) {
         pl->heap.release(off, words);
         return rc;
@@ -932,6 +933,7 @@ int fhp_pool_admit(fhp_pool* pl, const fhp_params* p, uint64_t steps, uint32_t* 
     s.heap_words = words;
     s.remaining = steps;
     pl->bands_used += bands;
+    pl->changed = 1;
     if (steps == 0) pl->finished.push_back(i);
     *slot = i;
     return FHP_OK;
@@ -941,32 +943,44 @@ int fhp_pool_tick(fhp_pool* pl, uint32_t passes) {
     if (!pl) return fail(FHP_E_INVAL, "pool is NULL");
     if (!passes) passes = 1;
     const uint32_t K = pl->eng.depth;
-    std::vector<fhp_sim*> act;
-    std::vector<uint32_t> lim, idx;
-    for (uint32_t i = 0; i < pl->slots.size(); i++) {
-        PoolSlot& s = pl->slots[i];
-        if (!s.used || s.remaining < K) continue;
-        const uint64_t full = s.remaining / K;
-        act.push_back(&s.sim);
-        lim.push_back((uint32_t)(full < passes ? full : passes));
-        idx.push_back(i);
-    }
-    if (!act.empty()) {
+    // The tables list every job with full passes left and give each its total
+    // count of full passes; the device counts them down, so the tables are
+    // rebuilt only when jobs arrive or leave.
+    if (pl->changed) {
+        std::vector<fhp_sim*> act;
+        std::vector<uint32_t> lim;
+        pl->table_slots.clear();
+        for (uint32_t i = 0; i < pl->slots.size(); i++) {
+            PoolSlot& s = pl->slots[i];
+            if (!s.used || s.remaining < K) continue;
+            const uint64_t full = s.remaining / K;
+            act.push_back(&s.sim);
+            lim.push_back((uint32_t)(full < 0xfffffffeull ? full : 0xfffffffeull));
+            pl->table_slots.push_back(i);
+        }
         int rc = engine_build(&pl->eng, act.data(), lim.data(), (uint32_t)act.size());
         if (rc) return rc;
-        rc = engine_run(&pl->eng, K, 1, passes);  // one pass per launch
+        pl->changed = 0;
+    }
+    std::vector<char> ran(pl->slots.size(), 0);
+    bool any = false;
+    for (uint32_t i : pl->table_slots) any |= pl->slots[i].remaining >= K;
+    if (any) {
+        int rc = engine_run(&pl->eng, K, 1, passes);  // one pass per launch
         if (rc) return rc;
-        for (size_t k = 0; k < act.size(); k++) {
-            PoolSlot& s = pl->slots[idx[k]];
-            s.sim.t += (uint64_t)lim[k] * K;
-            s.sim.cur ^= (int)(lim[k] & 1);
-            s.remaining -= (uint64_t)lim[k] * K;
+        for (uint32_t i : pl->table_slots) {  // host mirror of the device bookkeeping
+            PoolSlot& s = pl->slots[i];
+            const uint64_t full = s.remaining / K;
+            const uint64_t eff = full < passes ? full : passes;
+            if (!eff) continue;
+            s.sim.t += eff * K;
+            s.sim.cur ^= (int)(eff & 1);
+            s.remaining -= eff * K;
+            ran[i] = 1;
         }
     }
     // Jobs left with fewer than K steps finish on the single-lattice kernels;
     // every job that reached its last step in this tick is reported once.
-    std::vector<char> ran(pl->slots.size(), 0);
-    for (uint32_t i : idx) ran[i] = 1;
     for (uint32_t i = 0; i < pl->slots.size(); i++) {
         PoolSlot& s = pl->slots[i];
         if (!s.used) continue;
@@ -1019,9 +1033,10 @@ int fhp_pool_release(fhp_pool* pl, uint32_t slot) {
     if (slot >= pl->slots.size() || !pl->slots[slot].used)
         return fail(FHP_E_INVAL, "slot %u is not in use", slot);
     PoolSlot& s = pl->slots[slot];
-    // the memory may be reused by the next admission: wait for work on it
-    FHP_HIP_TRY(hipStreamSynchronize(pl->eng.st), "sync");
+    // No wait: work on this memory is already enqueued on the pool's stream,
+    // and whatever reuses it is enqueued after it.
     pl->heap.release(s.heap_off, s.heap_words);
+    pl->changed = 1;
     pl->bands_used -= s.sim.L.H / band_for(s.sim.L.H, pl->eng.band, pl->eng.depth);
     s.used = false;
     for (size_t k = 0; k < pl->finished.size(); k++)

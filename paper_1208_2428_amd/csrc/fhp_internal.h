@@ -100,9 +100,10 @@ namespace fhp {
 
 // Fills in a simulation whose planes start at `planes` (layout `lay`) with
 // reduction scratch `aux`, uploads the mask and writes the initial state.
-// Synchronises the stream.
+// Synchronises the stream when `sync` is set or a mask is given; otherwise the
+// initial state is only enqueued.
 int sim_setup(fhp_sim* s, const fhp_params* p, uint64_t* planes, const Layout& lay,
-              uint64_t* aux, hipStream_t st);
+              uint64_t* aux, hipStream_t st, bool sync = true);
 Lattice lattice_of(const fhp_sim* s);
 
 }  // namespace fhp
