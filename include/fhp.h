@@ -254,6 +254,15 @@ int fhp_pool_done(fhp_pool *pl, uint32_t *slots, uint32_t cap, uint32_t *n_done)
 /* Block sums (FHP_OBS_BLOCKS layout) of a job's current state; synchronises. */
 int fhp_pool_result(fhp_pool *pl, uint32_t slot, uint32_t block, int32_t *host_dst, size_t bytes);
 
+/* Asynchronous form of fhp_pool_result: enqueues the block sums of the job's
+ * state and their copy into host_dst (pinned host memory for a truly
+ * asynchronous copy; kept alive until fhp_pool_collected reports it ready). */
+int fhp_pool_collect(fhp_pool *pl, uint32_t slot, uint32_t block, int32_t *host_dst,
+                     size_t bytes);
+
+/* *ready = 1 once the last fhp_pool_collect of `slot` has completed. */
+int fhp_pool_collected(fhp_pool *pl, uint32_t slot, int *ready);
+
 /* Handle of the job in `slot` (observables, state access), owned by the pool. */
 int fhp_pool_member(fhp_pool *pl, uint32_t slot, fhp_sim **view);
 

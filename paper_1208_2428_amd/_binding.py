@@ -91,6 +91,10 @@ _SIGNATURES = {
                                      ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32)]),
     "fhp_pool_result": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                        ctypes.c_void_p, ctypes.c_size_t]),
+    "fhp_pool_collect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                        ctypes.c_void_p, ctypes.c_size_t]),
+    "fhp_pool_collected": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32,
+                                          ctypes.POINTER(ctypes.c_int)]),
     "fhp_pool_member": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32,
                                        ctypes.POINTER(ctypes.c_void_p)]),
     "fhp_pool_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),

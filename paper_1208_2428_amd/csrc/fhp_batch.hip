@@ -40,15 +40,20 @@ struct MemberDesc {
     const uint64_t* S;   // obstacle plane or nullptr
     uint64_t ps;         // plane stride in words
     uint64_t t0;         // steps completed
-    uint64_t key_chir, key_force, thr_force, chi_and, chi_or;
+    uint64_t key_chir, key_force;
+    uint32_t thr_force;       // floor(f * 2^38) < 2^32
+    uint32_t chi_and, chi_or; // chirality word = (hash & chi_and) | chi_or, per 32-bit half
     uint32_t H, wd, walls, cur;
     uint32_t passes;     // passes this member may still run (0xffffffff: no limit)
     uint32_t done_off;   // first band counter
     uint32_t nbands, T;
 };
 
+// Bands of lattices with the same width, height and band height: the row
+// geometry is uniform across the workgroup.
 struct GroupDesc {
-    uint32_t first, nseg, wd, T;
+    uint32_t first, nseg, wd, T, H, pad;
+    uint64_t ps;  // plane stride in words
 };
 
 struct BatchHeader {
@@ -84,7 +89,7 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
     for (;;) {
         if (lane == 0) bcast[0] = atomicAdd(&hdr->queue, 1u);
         __syncthreads();
-        const uint32_t item = bcast[0];
+        const uint32_t item = __builtin_amdgcn_readfirstlane(bcast[0]);
         __syncthreads();
         if (item >= n_items) break;
         const uint32_t p = item / n_groups;
@@ -131,7 +136,7 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
 
         // ---- one pass (K steps) of this lane's band: the sweep of the
         // single-lattice blocked kernel with per-lane lattice parameters.
-        const uint32_t H = M.H, wd = G.wd, T = G.T;
+        const uint32_t H = G.H, wd = G.wd, T = G.T;
         const uint32_t base = seg * wd;
         const uint32_t wl = base + (w ? w - 1 : wd - 1);
         const uint32_t wr = base + ((w + 1 == wd) ? 0 : w + 1);
@@ -139,10 +144,12 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
         const uint64_t* in = M.buf[cur];
         uint64_t* out = M.buf[cur ^ 1];
         const uint64_t* S = M.S;
-        const uint64_t ps = M.ps;
+        const uint64_t ps = G.ps;
         const uint32_t walls = M.walls;
         const uint64_t tp = M.t0 + (uint64_t)p * K;
-        const uint64_t chi_and = M.chi_and, chi_or = M.chi_or, thr = M.thr_force;
+        const uint64_t chi_and = ((uint64_t)M.chi_and << 32) | M.chi_and;
+        const uint64_t chi_or = ((uint64_t)M.chi_or << 32) | M.chi_or;
+        const uint64_t thr = M.thr_force;
         const uint64_t base_chi = word_base(M.key_chir, w);
         const uint64_t base_frc = word_base(M.key_force, w);
         const int y0 = (int)(b * T);
@@ -415,9 +422,9 @@ MemberDesc member_desc(const fhp_sim* s, uint32_t passes, uint32_t T, uint32_t d
     M.t0 = s->t;
     M.key_chir = s->D.key_chir;
     M.key_force = s->D.key_force;
-    M.thr_force = s->D.thr_force;
-    M.chi_and = (s->D.chir_mode == FHP_CHIR_HASH) ? ~0ull : 0ull;
-    M.chi_or = (s->D.chir_mode == FHP_CHIR_ONE) ? ~0ull : 0ull;
+    M.thr_force = (uint32_t)s->D.thr_force;
+    M.chi_and = (s->D.chir_mode == FHP_CHIR_HASH) ? ~0u : 0u;
+    M.chi_or = (s->D.chir_mode == FHP_CHIR_ONE) ? ~0u : 0u;
     M.H = s->L.H;
     M.wd = s->L.wd;
     M.walls = s->L.walls;
@@ -435,6 +442,7 @@ int engine_build(Engine* e, fhp_sim* const* sims, const uint32_t* limit, uint32_
     if (n > e->max_members) return fail(FHP_E_NOMEM, "%u lattices, room for %u", n, e->max_members);
     struct Seg {
         uint32_t wd, T, H, m, band;
+        uint64_t ps;
     };
     std::vector<MemberDesc> mem(n);
     std::vector<Seg> segs;
@@ -445,7 +453,8 @@ int engine_build(Engine* e, fhp_sim* const* sims, const uint32_t* limit, uint32_
         const uint32_t T = band_for(s->L.H, e->band, e->depth);
         mem[i] = member_desc(s, limit ? limit[i] : kNoLimit, T, done);
         done += mem[i].nbands;
-        for (uint32_t k = 0; k < mem[i].nbands; k++) segs.push_back({s->L.wd, T, s->L.H, i, k});
+        for (uint32_t k = 0; k < mem[i].nbands; k++)
+            segs.push_back({s->L.wd, T, s->L.H, i, k, (uint64_t)s->L.ps});
         if (s->L.wd > max_wd) max_wd = s->L.wd;
         force |= s->D.thr_force != 0;
         mask |= s->has_mask != 0;
@@ -455,21 +464,26 @@ int engine_build(Engine* e, fhp_sim* const* sims, const uint32_t* limit, uint32_
     uint32_t nt = e->nt_req ? e->nt_req : 64;
     const uint32_t need = (max_wd + 63) / 64 * 64;
     if (nt < need) nt = need;
-    // bands of equal (wd, T) share a workgroup; larger work first
+    // bands of equal (wd, H, T) share a workgroup; larger work first
     std::stable_sort(segs.begin(), segs.end(), [](const Seg& x, const Seg& y) {
         if (x.wd != y.wd) return x.wd > y.wd;
+        if (x.H != y.H) return x.H > y.H;
         return x.T > y.T;
     });
     std::vector<GroupDesc> groups;
     std::vector<uint32_t> sm(segs.size()), sb(segs.size());
     for (size_t k = 0; k < segs.size();) {
         GroupDesc g;
+        memset(&g, 0, sizeof(g));
         g.first = (uint32_t)k;
         g.wd = segs[k].wd;
         g.T = segs[k].T;
+        g.H = segs[k].H;
+        g.ps = segs[k].ps;
         g.nseg = 0;
         const uint32_t cap = nt / g.wd;
-        while (k < segs.size() && g.nseg < cap && segs[k].wd == g.wd && segs[k].T == g.T) {
+        while (k < segs.size() && g.nseg < cap && segs[k].wd == g.wd && segs[k].T == g.T &&
+               segs[k].H == g.H && segs[k].ps == g.ps) {
             sm[k] = segs[k].m;
             sb[k] = segs[k].band;
             g.nseg++;
@@ -666,6 +680,7 @@ struct PoolSlot {
     fhp_sim sim;
     size_t heap_off = 0, heap_words = 0;
     uint64_t remaining = 0;  // steps still to run
+    hipEvent_t collected = nullptr;  // recorded after an asynchronous result copy
 };
 
 struct fhp_pool {
@@ -1028,6 +1043,46 @@ int fhp_pool_result(fhp_pool* pl, uint32_t slot, uint32_t block, int32_t* host_d
     return fhp_observe(s, FHP_OBS_BLOCKS, block, host_dst, bytes);
 }
 
+int fhp_pool_collect(fhp_pool* pl, uint32_t slot, uint32_t block, int32_t* host_dst,
+                     size_t bytes) {
+    fhp_sim* s = nullptr;
+    int rc = fhp_pool_member(pl, slot, &s);
+    if (rc) return rc;
+    if (!host_dst) return fail(FHP_E_INVAL, "NULL destination");
+    if (block == 0 || (block < 64 ? (64 % block) : (block % 64)))
+        return fail(FHP_E_INVAL, "block %u must divide 64 or be a multiple of 64", block);
+    const uint32_t bw = (s->L.W + block - 1) / block, bh = (s->L.H + block - 1) / block;
+    const size_t need = (size_t)bw * bh * 3 * sizeof(int32_t);
+    if (bytes < need) return fail(FHP_E_NOMEM, "destination of %zu bytes, %zu needed", bytes, need);
+    if (need > s->lay.buf_words * sizeof(uint64_t))
+        return fail(FHP_E_INVAL, "block %u too small for an asynchronous result", block);
+    PoolSlot& ps = pl->slots[slot];
+    if (!ps.collected) FHP_HIP_TRY(hipEventCreateWithFlags(&ps.collected, hipEventDisableTiming),
+                                   "event");
+    int32_t* stage = (int32_t*)s->buf[1 - s->cur];  // the idle buffer
+    FHP_HIP_TRY(launch_observe_blocks(s->buf[s->cur], lattice_of(s), block, 0, bh, stage, s->st),
+                "blocks");
+    FHP_HIP_TRY(hipMemcpyAsync(host_dst, stage, need, hipMemcpyDeviceToHost, s->st), "copy");
+    FHP_HIP_TRY(hipEventRecord(ps.collected, s->st), "event");
+    return FHP_OK;
+}
+
+int fhp_pool_collected(fhp_pool* pl, uint32_t slot, int* ready) {
+    if (!pl || !ready) return fail(FHP_E_INVAL, "NULL argument");
+    if (slot >= pl->slots.size() || !pl->slots[slot].used)
+        return fail(FHP_E_INVAL, "slot %u is not in use", slot);
+    const PoolSlot& ps = pl->slots[slot];
+    if (!ps.collected) return fail(FHP_E_STATE, "slot %u: no result was collected", slot);
+    hipError_t e = hipEventQuery(ps.collected);
+    if (e == hipErrorNotReady) {
+        *ready = 0;
+        return FHP_OK;
+    }
+    FHP_HIP_TRY(e, "event");
+    *ready = 1;
+    return FHP_OK;
+}
+
 int fhp_pool_release(fhp_pool* pl, uint32_t slot) {
     if (!pl) return fail(FHP_E_INVAL, "pool is NULL");
     if (slot >= pl->slots.size() || !pl->slots[slot].used)
@@ -1066,6 +1121,8 @@ int fhp_pool_sync(fhp_pool* pl) {
 void fhp_pool_destroy(fhp_pool* pl) {
     if (!pl) return;
     (void)hipStreamSynchronize(pl->eng.st);
+    for (auto& s : pl->slots)
+        if (s.collected) (void)hipEventDestroy(s.collected);
     engine_free(&pl->eng);
     delete pl;
 }

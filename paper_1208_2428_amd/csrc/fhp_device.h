@@ -67,51 +67,50 @@ FHP_HD uint32_t or3(uint32_t a, uint32_t b, uint32_t c) { return lop3<kA | kB | 
 // bounce-back on solid nodes, then forcing).  a[0..5] moving channels, a[6]
 // rest, s solid, chi chirality, coin forcing coin (at most one bit).
 //
-// Every colliding state maps to a function of the two channels next to each
-// output channel j (indices mod 6):
+// Every colliding state maps each output channel j to a function of the two
+// channels next to it, A = a_{j-1} and B = a_{j+1} (indices mod 6):
 //   R1 head-on pair alone (rest particle a spectator): the pair turns by
-//      +60 deg (chi = 1) or -60 deg (chi = 0): o_j = chi ? a_{j-1} : a_{j+1};
-//   R2 {0,2,4} <-> {1,3,5} without rest particle: o_j = a_{j-1} (= a_{j+1});
-//   R3 one particle c plus rest -> {c-1, c+1}: o_j = a_{j-1} | a_{j+1}, and
-//      {c-1, c+1} without rest -> c plus rest: o_j = a_{j-1} & a_{j+1};
-//      i.e. o_j = maj(rest, a_{j-1}, a_{j+1}) and the rest bit flips.
-// The rule that applies is found from the number n of moving particles
-// (a full-adder tree), whether an opposite pair is present (P) and whether
-// two neighbouring channels are occupied (adj): R1 = (n = 2) & P;
-// R3 = rest ? (n = 1) : ((n = 2) & !P & !adj); R2 = (n = 3), no rest,
-// channels 0, 2, 4 equal.
+//      +60 deg (chi = 1) or -60 deg (chi = 0): o_j = chi ? A : B;
+//   R2 {0,2,4} <-> {1,3,5} without rest particle: o_j = A (= B);
+//   R3 one particle c plus rest -> {c-1, c+1}: o_j = A | B, and {c-1, c+1}
+//      without rest -> c plus rest: o_j = A & B; i.e. o_j = maj(rest, A, B),
+//      and the rest bit flips.
+// Both forms are "A where A = B, else Z": Z = (chi XNOR A) for R1/R2 and
+// Z = rest for R3.  The rule that applies comes from the number n of moving
+// particles, counted by parity class (even channels 0, 2, 4 and odd 1, 3, 5
+// with full adders): R1 = (n = 2) & (an opposite pair present);
+// R3 = rest ? (n = 1) : ((n = 2) & both particles in one class, i.e. at
+// 120 deg); R2 = (n = 3) without rest, channels 0, 2, 4 equal.
 FHP_HD void update32(const uint32_t a[7], uint32_t s, uint32_t chi, uint32_t coin, uint32_t o[7]) {
     const uint32_t r = a[6];
-    // popcount of the six moving channels: n = n0 + 2 n1 + 4 n2
-    const uint32_t sa = xor3(a[0], a[1], a[2]), ca = maj3(a[0], a[1], a[2]);
-    const uint32_t sb = xor3(a[3], a[4], a[5]), cb = maj3(a[3], a[4], a[5]);
-    const uint32_t n0 = sa ^ sb, c0 = sa & sb;
-    const uint32_t n1 = xor3(ca, cb, c0), n2 = maj3(ca, cb, c0);
+    // n = n0 + 2 n1 + 4 n2; se = parity of the even-class count
+    const uint32_t se = xor3(a[0], a[2], a[4]), ce = maj3(a[0], a[2], a[4]);
+    const uint32_t so = xor3(a[1], a[3], a[5]), co = maj3(a[1], a[3], a[5]);
+    const uint32_t n0 = se ^ so, c0 = se & so;
+    const uint32_t n1 = xor3(ce, co, c0), n2 = maj3(ce, co, c0);
     const uint32_t is1 = lop3<kA & ~kB & ~kC>(n0, n1, n2);
     const uint32_t is2 = lop3<~kA & kB & ~kC>(n0, n1, n2);
-    const uint32_t is3 = lop3<kA & kB & ~kC>(n0, n1, n2);
+    const uint32_t is3 = n0 & n1;  // n = 7 cannot occur
     // an opposite (head-on) pair is present
     uint32_t pp = a[0] & a[3];
     pp = lop3<kA | (kB & kC)>(pp, a[1], a[4]);
     pp = lop3<kA | (kB & kC)>(pp, a[2], a[5]);
-    // two neighbouring channels are occupied
-    const uint32_t t1 = lop3<(kA & kB) | (kB & kC)>(a[0], a[1], a[2]);
-    const uint32_t t2 = lop3<(kA & kB) | (kB & kC)>(a[2], a[3], a[4]);
-    const uint32_t t3 = lop3<(kA & kB) | (kB & kC)>(a[4], a[5], a[0]);
-    const uint32_t adj = or3(t1, t2, t3);
     const uint32_t eq024 = lop3<(kA & kB & kC) | (~kA & ~kB & ~kC)>(a[0], a[2], a[4]);
-    const uint32_t tri = lop3<kA & kB & ~kC>(is3, eq024, r);          // R2
-    const uint32_t head = is2 & pp;                                    // R1
-    const uint32_t v120 = lop3<kA & ~kB & ~kC>(is2, pp, adj);         // two at 120 deg
-    const uint32_t c12 = lop3<(kA | kB) & ~kC>(head, tri, s);         // R1 or R2, fluid
-    const uint32_t c3 = lop3<((kA & kB) | (~kA & kC)) & 0xFF>(r, is1, v120) & ~s;  // R3, fluid
+    const uint32_t tri = lop3<kA & kB & ~kC>(is3, eq024, r);            // R2
+    const uint32_t c12 = lop3<((kA & kB) | kC) & 0xFF>(is2, pp, tri) & ~s;  // R1 or R2, fluid
+    const uint32_t f3 = lop3<kA & ~kB & ~kC>(is2, se, s);               // two at 120 deg, fluid
+    const uint32_t e3 = lop3<kA & kB & ~kC>(r, is1, s);                 // one + rest, fluid
+    const uint32_t c3 = lop3<(kA & kB) | (~kA & kC)>(r, e3, f3);        // R3, fluid
+    const uint32_t zc = lop3<(kA & ~kB) | (~kA & kC)>(c12, chi, r);     // c12 ? ~chi : r
+    const uint32_t any = c12 | c3;                                      // a rule applies
+    const uint32_t keep = lop3<~(kA | kB)>(any, s, 0);                  // unchanged node
 #pragma unroll
     for (int j = 0; j < 6; j++) {
         const uint32_t am = a[(j + 5) % 6], ap = a[(j + 1) % 6];
-        const uint32_t rot = mux3(chi, am, ap);
-        const uint32_t r3 = maj3(r, am, ap);
-        const uint32_t base = mux3(s, a[(j + 3) % 6], a[j]);  // bounce-back or unchanged
-        o[j] = mux3(c12, rot, mux3(c3, r3, base));
+        const uint32_t z = lop3<kA ^ (kB & kC)>(zc, c12, am);             // zc ^ (c12 & A)
+        const uint32_t sp = lop3<(((kA ^ kB) & kC) | (~(kA ^ kB) & kA)) & 0xFF>(am, ap, z);
+        const uint32_t alt = mux3(any, sp, a[(j + 3) % 6]);                // collide or bounce
+        o[j] = mux3(keep, a[j], alt);
     }
     o[6] = r ^ c3;
     // forcing: bits 5 -> 2 where the coin is up, on fluid nodes with o5 set, o2 clear

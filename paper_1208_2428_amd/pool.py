@@ -34,6 +34,7 @@ class Pool:
         self._h = h
         self.max_slots = max_slots
         self._shapes = {}
+        self._pinned = {}
         if depth or band or group_threads:
             B.check(lib.fhp_pool_set_tiling(h, int(depth), int(band), int(group_threads)))
 
@@ -72,6 +73,23 @@ class Pool:
                                           out.ctypes.data_as(ctypes.c_void_p), out.nbytes))
         return out
 
+    def collect(self, slot: int, block: int = 16) -> np.ndarray:
+        """Enqueues the job's block sums into a pinned host array and returns
+        it; valid once ``collected(slot)`` is True."""
+        W, H = self._shapes[slot]
+        shape = ((H + block - 1) // block, (W + block - 1) // block, 3)
+        buf = torch.empty(shape, dtype=torch.int32, pin_memory=True)
+        out = buf.numpy()
+        B.check(self._lib.fhp_pool_collect(self._h, int(slot), int(block),
+                                           ctypes.c_void_p(buf.data_ptr()), out.nbytes))
+        self._pinned[slot] = buf
+        return out
+
+    def collected(self, slot: int) -> bool:
+        r = ctypes.c_int()
+        B.check(self._lib.fhp_pool_collected(self._h, int(slot), ctypes.byref(r)))
+        return bool(r.value)
+
     def member(self, slot: int):
         v = ctypes.c_void_p()
         B.check(self._lib.fhp_pool_member(self._h, int(slot), ctypes.byref(v)))
@@ -84,6 +102,7 @@ class Pool:
     def release(self, slot: int) -> None:
         B.check(self._lib.fhp_pool_release(self._h, int(slot)))
         self._shapes.pop(slot, None)
+        self._pinned.pop(slot, None)
 
     def usage(self) -> dict:
         a, u, f = ctypes.c_uint32(), ctypes.c_size_t(), ctypes.c_size_t()

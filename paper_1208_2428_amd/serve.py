@@ -15,6 +15,7 @@ import time
 from collections import deque
 
 import numpy as np
+import torch
 
 from . import workloads as WL
 from .pool import Pool
@@ -40,6 +41,7 @@ class Server:
                          group_threads=group_threads)
         self.passes = passes_per_tick
         self.block = block
+        self.ticks_ahead = 2  # ticks the host may enqueue before waiting for the GPU
 
     def run(self, requests: list[WL.Request], realtime: bool = True, keep_results=None,
             log=None) -> dict:
@@ -52,6 +54,8 @@ class Server:
         pending = deque(enumerate(requests))
         queue: deque = deque()
         inflight: dict[int, tuple[int, WL.Request]] = {}
+        collecting: dict[int, np.ndarray] = {}
+        in_flight: deque = deque()
         lat, results = [], {}
         node_updates = 0
         ticks = max_queue = max_active = 0
@@ -72,16 +76,29 @@ class Server:
                 if pending:
                     time.sleep(max(0.0, min(0.01, pending[0][1].arrival - now)))
                 continue
-            pool.tick(self.passes)
-            ticks += 1
+            any_work = len(collecting) < len(inflight)  # some job still has steps to run
+            if not any_work:
+                time.sleep(0.0002)  # only result copies in flight
+            if any_work:
+                pool.tick(self.passes)
+                ticks += 1
+                ev = torch.cuda.Event()
+                ev.record(pool.stream)
+                in_flight.append(ev)
+                while len(in_flight) > self.ticks_ahead:  # bounded run-ahead of the host
+                    in_flight.popleft().synchronize()
+            # finished jobs: enqueue their results (pinned, asynchronous) ...
             for slot in pool.done():
+                collecting[slot] = pool.collect(slot, self.block)
+            # ... and hand back the ones whose copy has completed
+            for slot in [s for s in collecting if pool.collected(s)]:
+                blocks = collecting.pop(slot)
                 idx, r = inflight.pop(slot)
-                blocks = pool.result(slot, self.block)  # waits for the job's last pass
                 t_done = time.perf_counter() - start
                 lat.append(t_done - (r.arrival if realtime else 0.0))
                 node_updates += r.side * r.side * r.steps
                 if keep_results is not None and idx in keep_results:
-                    results[idx] = blocks
+                    results[idx] = blocks.copy()
                 pool.release(slot)
             if log and ticks % 200 == 0:
                 log(f"serve: t={time.perf_counter() - start:.1f}s done={len(lat)} "

@@ -81,3 +81,26 @@ def test_null_handle_calls_fail_cleanly(lib):
     assert lib.fhp_sync(None) == B.E_INVAL
     assert lib.fhp_set_depth(None, 1) == B.E_INVAL
     lib.fhp_destroy(None)
+
+
+def test_batch_and_pool_argument_checks(lib):
+    n = ctypes.c_size_t()
+    arr = (B.Params * 2)()
+    arr[0], _ = B.make_params(128, 64)
+    arr[1], _ = B.make_params(128, 4)          # below the batch's minimum height
+    assert lib.fhp_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == B.E_INVAL
+    arr[1], _ = B.make_params(256, 32)
+    assert lib.fhp_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == B.OK
+    planes = (128 * 64 + 256 * 32) // 8
+    assert n.value >= 15 * planes
+    assert lib.fhp_batch_workspace_bytes(arr, 0, ctypes.byref(n)) == B.E_INVAL
+    h = ctypes.c_void_p()
+    assert lib.fhp_batch_create(arr, 2, None, n.value, None, ctypes.byref(h)) == B.E_INVAL
+    assert lib.fhp_pool_workspace_bytes(0, 16, 1 << 20, ctypes.byref(n)) == B.E_INVAL
+    assert lib.fhp_pool_workspace_bytes(16, 1024, 1 << 20, ctypes.byref(n)) == B.OK
+    assert n.value > 1 << 20
+    assert lib.fhp_pool_create(None, n.value, 16, 1024, None, ctypes.byref(h)) == B.E_INVAL
+    assert lib.fhp_pool_create(ctypes.c_void_p(256), 1024, 16, 1024, None,
+                               ctypes.byref(h)) == B.E_NOMEM   # arena smaller than its tables
+    assert lib.fhp_pool_tick(None, 1) == B.E_INVAL
+    assert lib.fhp_batch_step(None, 1) == B.E_INVAL

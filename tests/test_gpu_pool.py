@@ -94,3 +94,22 @@ def test_serving_loop_results_match_alone():
         np.testing.assert_array_equal(out["results"][i], s.observe_blocks(16), err_msg=str(i))
         s.close()
     srv.close()
+
+
+def test_asynchronous_collection_matches_result():
+    pool = Pool(Pool.arena_bytes_for(4, 1024, 16 << 20), max_slots=4, max_bands=1024)
+    p = dict(width=256, height=128, seed=21, fill=0.3, force_rate=1e-3, walls=True)
+    slot = pool.admit(18, **p)
+    while not (done := pool.done()):
+        pool.tick(2)
+    assert done == [slot]
+    out = pool.collect(slot, 16)
+    for _ in range(2_000_000):
+        if pool.collected(slot):
+            break
+    else:
+        pytest.fail("the result copy did not complete")
+    np.testing.assert_array_equal(out, pool.result(slot, 16))
+    ref = oracle_state(p, 18)
+    np.testing.assert_array_equal(out, oracle.observe_blocks(ref, 16))
+    pool.release(slot)

@@ -1,0 +1,71 @@
+"""The seeded input generators (CPU only): the porous mask, the ensemble and
+the request stream have the sizes and distributions their recipes state."""
+import math
+
+import numpy as np
+
+from paper_1208_2428_amd import workloads as WL
+
+
+def test_porous_mask_recipe():
+    W, H = 1024, 512
+    m = WL.porous_mask(W, H, seed=33)
+    frac = m.mean()
+    assert 0.05 <= frac < 0.06
+    # deterministic
+    assert np.array_equal(m, WL.porous_mask(W, H, seed=33))
+    assert not np.array_equal(m, WL.porous_mask(W, H, seed=34))
+
+
+def test_porous_disks_are_separated():
+    # every solid node lies within r of exactly one accepted centre: recover
+    # the disks by flood fill on the triangular lattice and check sizes
+    W, H = 512, 256
+    m = WL.porous_mask(W, H, seed=5, rmin=8, rmax=12, frac=0.05)
+    seen = np.zeros_like(m, dtype=bool)
+    sizes = []
+    for y0, x0 in zip(*np.nonzero(m)):
+        if seen[y0, x0]:
+            continue
+        stack, n = [(y0, x0)], 0
+        seen[y0, x0] = True
+        while stack:
+            y, x = stack.pop()
+            n += 1
+            for dx, dy in ((1, 0), (-1, 0), (0, 1), (0, -1),
+                           (1 if y % 2 else -1, 1), (1 if y % 2 else -1, -1)):
+                yy, xx = (y + dy) % H, (x + dx) % W
+                if m[yy, xx] and not seen[yy, xx]:
+                    seen[yy, xx] = True
+                    stack.append((yy, xx))
+        sizes.append(n)
+    # a disk of radius r on the triangular lattice has about (2 pi / sqrt 3) r^2 nodes
+    lo = 2 * math.pi / math.sqrt(3) * 8 ** 2 * 0.8
+    hi = 2 * math.pi / math.sqrt(3) * 12 ** 2 * 1.2
+    assert all(lo <= s <= hi for s in sizes), (min(sizes), max(sizes))
+
+
+def test_ensemble_recipe():
+    ms = WL.batch_members(n=512, seed=4)
+    sides = np.array([m.width for m in ms])
+    assert len(ms) == 512 and all(m.width == m.height for m in ms)
+    assert sides.min() >= 128 and sides.max() <= 2048 and np.all(sides % 64 == 0)
+    assert len(set(sides)) >= 25                       # 31 possible sides
+    fills = np.array([m.fill for m in ms])
+    assert fills.min() >= 0.1 and fills.max() <= 0.4
+    assert len({m.seed for m in ms}) == 512
+
+
+def test_request_stream_recipe():
+    rs = WL.request_stream(n=2000, rate=200.0, seed=5)
+    t = np.array([r.arrival for r in rs])
+    gaps = np.diff(np.concatenate([[0.0], t]))
+    assert np.all(gaps >= 0)
+    assert abs(gaps.mean() - 1 / 200) < 5 * (1 / 200) / math.sqrt(2000)
+    sides = np.array([r.side for r in rs])
+    assert np.all(sides % 64 == 0) and sides.min() >= 256 and sides.max() <= 8192
+    steps = np.array([r.steps for r in rs])
+    assert steps.min() >= 100 and steps.max() <= 10000
+    # log-uniform: the median is near sqrt(100 * 10000) = 1000
+    assert 800 < np.median(steps) < 1250
+    assert all(r.walls and r.fill == 0.25 and r.force_rate == 1e-3 for r in rs)
