@@ -29,6 +29,7 @@
 #include <vector>
 
 #include "fhp_device.h"
+#include "fhp_groups.h"
 #include "fhp_internal.h"
 #include "fhp_sweep.h"
 
@@ -47,13 +48,6 @@ struct MemberDesc {
     uint32_t passes;     // passes this member may still run (0xffffffff: no limit)
     uint32_t done_off;   // first band counter
     uint32_t nbands, T;
-};
-
-// Bands of lattices with the same width, height and band height: the row
-// geometry is uniform across the workgroup.
-struct GroupDesc {
-    uint32_t first, nseg, wd, T, H, pad;
-    uint64_t ps;  // plane stride in words
 };
 
 struct BatchHeader {
@@ -436,64 +430,56 @@ MemberDesc member_desc(const fhp_sim* s, uint32_t passes, uint32_t T, uint32_t d
     return M;
 }
 
+int engine_grid(uint32_t K, bool force, bool mask, uint32_t nt, uint32_t* grid);
+
 // Builds the member and group tables of sims[0..n) (pass limits `limit`, or
 // no limit) and enqueues their upload on the engine's stream.
 int engine_build(Engine* e, fhp_sim* const* sims, const uint32_t* limit, uint32_t n) {
     if (n > e->max_members) return fail(FHP_E_NOMEM, "%u lattices, room for %u", n, e->max_members);
-    struct Seg {
-        uint32_t wd, T, H, m, band;
-        uint64_t ps;
-    };
     std::vector<MemberDesc> mem(n);
-    std::vector<Seg> segs;
+    std::vector<uint32_t> bandT(n), order(n);
     uint32_t done = 0, max_wd = 0;
     bool force = false, mask = false;
     for (uint32_t i = 0; i < n; i++) {
         const fhp_sim* s = sims[i];
-        const uint32_t T = band_for(s->L.H, e->band, e->depth);
-        mem[i] = member_desc(s, limit ? limit[i] : kNoLimit, T, done);
+        bandT[i] = band_for(s->L.H, e->band, e->depth);
+        mem[i] = member_desc(s, limit ? limit[i] : kNoLimit, bandT[i], done);
         done += mem[i].nbands;
-        for (uint32_t k = 0; k < mem[i].nbands; k++)
-            segs.push_back({s->L.wd, T, s->L.H, i, k, (uint64_t)s->L.ps});
+        order[i] = i;
         if (s->L.wd > max_wd) max_wd = s->L.wd;
         force |= s->D.thr_force != 0;
         mask |= s->has_mask != 0;
     }
+    // bands of equal (wd, H, T) share a workgroup: order the members by that
+    // class, larger work first, and list their bands in that order
+    std::sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+        const Lattice &a = sims[x]->L, &b = sims[y]->L;
+        if (a.wd != b.wd) return a.wd > b.wd;
+        if (a.H != b.H) return a.H > b.H;
+        if (bandT[x] != bandT[y]) return bandT[x] > bandT[y];
+        if (a.ps != b.ps) return a.ps > b.ps;
+        return x < y;
+    });
+    std::vector<BandSeg> segs;
+    segs.reserve(done);
+    for (uint32_t i : order)
+        for (uint32_t k = 0; k < mem[i].nbands; k++)
+            segs.push_back({sims[i]->L.wd, bandT[i], sims[i]->L.H, i, k, (uint64_t)sims[i]->L.ps});
     if (segs.size() > e->max_segs)
         return fail(FHP_E_NOMEM, "%zu bands, room for %u", segs.size(), e->max_segs);
     uint32_t nt = e->nt_req ? e->nt_req : 64;
     const uint32_t need = (max_wd + 63) / 64 * 64;
     if (nt < need) nt = need;
-    // bands of equal (wd, H, T) share a workgroup; larger work first
-    std::stable_sort(segs.begin(), segs.end(), [](const Seg& x, const Seg& y) {
-        if (x.wd != y.wd) return x.wd > y.wd;
-        if (x.H != y.H) return x.H > y.H;
-        return x.T > y.T;
-    });
+    uint32_t grid = 0;
+    if (n) {
+        const int rc = engine_grid(e->depth, force, mask, nt, &grid);
+        if (rc) return rc;
+    }
     std::vector<GroupDesc> groups;
     std::vector<uint32_t> sm(segs.size()), sb(segs.size());
-    for (size_t k = 0; k < segs.size();) {
-        GroupDesc g;
-        memset(&g, 0, sizeof(g));
-        g.first = (uint32_t)k;
-        g.wd = segs[k].wd;
-        g.T = segs[k].T;
-        g.H = segs[k].H;
-        g.ps = segs[k].ps;
-        g.nseg = 0;
-        const uint32_t cap = nt / g.wd;
-        while (k < segs.size() && g.nseg < cap && segs[k].wd == g.wd && segs[k].T == g.T &&
-               segs[k].H == g.H && segs[k].ps == g.ps) {
-            sm[k] = segs[k].m;
-            sb[k] = segs[k].band;
-            g.nseg++;
-            k++;
-        }
-        groups.push_back(g);
-    }
-    std::stable_sort(groups.begin(), groups.end(), [](const GroupDesc& x, const GroupDesc& y) {
-        return (uint64_t)x.nseg * x.wd * x.T > (uint64_t)y.nseg * y.wd * y.T;
-    });
+    pack_groups(segs, nt, groups, sm.data(), sb.data());
+    split_last_round(groups, nt, grid);
+    order_groups(groups, nt);
     BatchHeader h;
     memset(&h, 0, sizeof(h));
     h.n_groups = (uint32_t)groups.size();
@@ -528,17 +514,25 @@ int engine_build(Engine* e, fhp_sim* const* sims, const uint32_t* limit, uint32_
     return FHP_OK;
 }
 
-int engine_kernel(Engine* e, uint32_t K, BatchLaunch* fn, uint32_t* grid) {
+// Persistent grid: every workgroup that fits on the device at once.
+int engine_grid(uint32_t K, bool force, bool mask, uint32_t nt, uint32_t* grid) {
+    BatchLaunch fn;
     BatchKernel kern;
-    if (!pick_kernel(K, e->force, e->mask, fn, &kern)) return fail(FHP_E_INVAL, "depth %u", K);
+    if (!pick_kernel(K, force, mask, &fn, &kern)) return fail(FHP_E_INVAL, "depth %u", K);
     int per_cu = 0, dev = 0, cus = 0;
     FHP_HIP_TRY(hipGetDevice(&dev), "device");
     FHP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "attr");
-    FHP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)e->nt,
-                                                            (2 * e->nt + 1) * sizeof(uint32_t)),
+    FHP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)nt,
+                                                            (2 * nt + 1) * sizeof(uint32_t)),
                 "occupancy");
     *grid = (uint32_t)((per_cu < 1 ? 1 : per_cu) * cus);
     return FHP_OK;
+}
+
+int engine_kernel(Engine* e, uint32_t K, BatchLaunch* fn, uint32_t* grid) {
+    BatchKernel kern;
+    if (!pick_kernel(K, e->force, e->mask, fn, &kern)) return fail(FHP_E_INVAL, "depth %u", K);
+    return engine_grid(K, e->force, e->mask, e->nt, grid);
 }
 
 int engine_enqueue(Engine* e, uint32_t K, uint32_t passes, uint32_t launches) {

@@ -31,3 +31,18 @@ def test_update_matches_oracle_table_exhaustively(checker):
     r = subprocess.run([checker], capture_output=True, text=True)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "OK" in r.stdout
+
+
+def test_batch_band_packing(tmp_path):
+    """Packing of lattice bands into the batch kernel's work items (host code
+    of the batch engine, built with g++): coverage, class purity, fit, the
+    split of a pass's last round and the queue order."""
+    if not shutil.which("g++"):
+        pytest.skip("g++ not available")
+    exe = str(tmp_path / "groups_check")
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I",
+                    os.path.join(ROOT, "paper_1208_2428_amd", "csrc"),
+                    os.path.join(HERE, "native", "groups_check.cpp"), "-o", exe], check=True)
+    r = subprocess.run([exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert r.stdout.startswith("OK")
