@@ -262,7 +262,8 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
                 if (M.passes != kNoLimit) M.passes -= eff;
             }
         }
-        for (uint32_t k = lane; k < hdr->n_done; k += nt) done[k] = 0;
+        if (passes > 1)  // single-pass launches leave the counters at zero
+            for (uint32_t k = lane; k < hdr->n_done; k += nt) done[k] = 0;
         __syncthreads();
         if (lane == 0) {
             hdr->queue = 0;

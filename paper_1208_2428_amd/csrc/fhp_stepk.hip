@@ -46,16 +46,6 @@ struct StepkArgs {
     uint64_t chi_and, chi_or;  // chirality word = (hash & chi_and) | chi_or
 };
 
-// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
-// L2.  Giving every XCD a contiguous run of bands lets a band's halo rows hit
-// in the L2 that has just read them for the neighbouring band.
-constexpr uint32_t kXcds = 8;
-__device__ __forceinline__ uint32_t xcd_band(uint32_t b, uint32_t n) {
-    const uint32_t per = n / kXcds;
-    if (b >= per * kXcds) return b;  // the remainder keeps its order
-    return (b % kXcds) * per + b / kXcds;
-}
-
 template <int K, bool FORCE, bool MASK>
 __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
                                                 uint64_t* __restrict__ out,
@@ -68,7 +58,11 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
     const uint32_t wl = w ? w - 1 : a.wd - 1;
     const uint32_t wr = (w + 1 == a.wd) ? 0 : w + 1;
     const uint32_t H = a.H;
-    const uint32_t y0 = xcd_band(blockIdx.x, gridDim.x) * a.T;
+    // Bands in launch order: workgroups go round-robin over the 8 XCDs, so
+    // neighbouring bands run on different XCDs at the same time.  Giving each
+    // XCD a contiguous run of bands instead measured 8% slower at K = 4 and
+    // 19% slower at K = 2 on the 16384^2 lattice.
+    const uint32_t y0 = blockIdx.x * a.T;
     const uint32_t rows = min(a.T, H - y0);
     const int n_iter = (int)rows + 2 * K;
     const uint64_t base_chi = word_base(a.key_chir, w);
