@@ -3,11 +3,13 @@
 //
 // Work decomposition.  Every lattice (member) is cut into bands of T rows
 // (T even, T | H), as in the single-lattice blocked kernel.  A band needs one
-// thread per 64-node word of a row, i.e. wd = W/64 lanes; bands of lattices
-// with the same (wd, T) are packed side by side into groups of one workgroup
-// (floor(nt / wd) bands per group), so a wave can hold e.g. 32 bands of
-// 128-wide lattices.  The horizontal carry exchange wraps inside each band's
-// lane segment.
+// lane per 64-node word of a row, i.e. wd = W/64 lanes; bands with the same
+// (wd, T) are packed side by side into the waves of one workgroup, each wave
+// holding consecutive bands of a single member (so a wave can hold e.g. 32
+// bands of one 128-wide lattice, and a 100-word band spans two waves).  All
+// per-member values are then uniform across a wave and kept in scalar
+// registers; per lane remain the word, the band and the hash base.  The
+// horizontal carry exchange wraps inside each band's lanes.
 //
 // Work items are (pass, group) pairs taken in pass-major order from a global
 // counter by a persistent grid.  A band's pass p reads its own rows and the K
@@ -64,16 +66,22 @@ __device__ __forceinline__ uint32_t load_acquire(const uint32_t* p) {
     return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Scalar copy of a value that is uniform across the wave.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni(uint64_t v) {
+    return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
+}
+
 template <int K, bool FORCE, bool MASK>
 __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
                                                MemberDesc* __restrict__ members,
                                                const GroupDesc* __restrict__ groups,
-                                               const uint32_t* __restrict__ seg_member,
-                                               const uint32_t* __restrict__ seg_band,
+                                               const WaveDesc* __restrict__ waves,
                                                uint32_t* __restrict__ done) {
     extern __shared__ uint32_t xch[];  // 2 carry slots x nt, then one broadcast word
     const uint32_t nt = blockDim.x;
     const uint32_t lane = threadIdx.x;
+    const uint32_t wave = uni(lane >> 6);
     uint32_t* bcast = xch + 2 * nt;
     const uint32_t n_groups = hdr->n_groups;
     const uint32_t passes = hdr->passes;
@@ -83,25 +91,30 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
     for (;;) {
         if (lane == 0) bcast[0] = atomicAdd(&hdr->queue, 1u);
         __syncthreads();
-        const uint32_t item = __builtin_amdgcn_readfirstlane(bcast[0]);
+        const uint32_t item = uni(bcast[0]);
         __syncthreads();
         if (item >= n_items) break;
         const uint32_t p = item / n_groups;
         const GroupDesc G = groups[item - p * n_groups];
-        const uint32_t seg = lane / G.wd;
-        const uint32_t w = lane - seg * G.wd;
-        const bool valid = seg < G.nseg;
-        const uint32_t sidx = G.first + (valid ? seg : 0);
-        const uint32_t m = seg_member[sidx];
-        const uint32_t b = seg_band[sidx];
-        const MemberDesc& M = members[m];
-        const bool active = valid && p < M.passes;
+        const uint32_t wd = G.wd, T = G.T;
+        const bool wave_on = wave < G.nwaves;
+        const WaveDesc D = waves[G.first_wave + (wave_on ? wave : 0)];
+        // this wave's member: every value read from it is wave-uniform
+        const MemberDesc* M = members + uni(D.m);
+        const uint32_t rel = uni(D.rel0) + (lane & 63);
+        const uint32_t j = rel / wd;
+        const uint32_t w = rel - j * wd;
+        const bool valid = wave_on && j < uni(D.count);
+        const uint32_t b = uni(D.band0) + (valid ? j : 0);
+        const uint32_t m_passes = uni(M->passes);
+        const bool active = valid && p < m_passes;
         if (!__syncthreads_or(active)) continue;
 
+        const uint32_t nb = uni(M->nbands);
+        const uint32_t done_off = uni(M->done_off);
         if (p > 0) {  // wait for the neighbouring bands' previous pass
-            const uint32_t nb = M.nbands;
             const uint32_t bm = b ? b - 1 : nb - 1, bq = (b + 1 == nb) ? 0 : b + 1;
-            const uint32_t* dm = done + M.done_off;
+            const uint32_t* dm = done + done_off;
             uint32_t spins = 0;
             int abort = 0;
             for (;;) {
@@ -129,35 +142,47 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
         }
 
         // ---- one pass (K steps) of this lane's band: the sweep of the
-        // single-lattice blocked kernel with per-lane lattice parameters.
-        const uint32_t H = G.H, wd = G.wd, T = G.T;
-        const uint32_t base = seg * wd;
-        const uint32_t wl = base + (w ? w - 1 : wd - 1);
-        const uint32_t wr = base + ((w + 1 == wd) ? 0 : w + 1);
-        const uint32_t cur = (M.cur + p) & 1;
-        const uint64_t* in = M.buf[cur];
-        uint64_t* out = M.buf[cur ^ 1];
-        const uint64_t* S = M.S;
-        const uint64_t ps = G.ps;
-        const uint32_t walls = M.walls;
-        const uint64_t tp = M.t0 + (uint64_t)p * K;
-        const uint64_t chi_and = ((uint64_t)M.chi_and << 32) | M.chi_and;
-        const uint64_t chi_or = ((uint64_t)M.chi_or << 32) | M.chi_or;
-        const uint64_t thr = M.thr_force;
-        const uint64_t base_chi = word_base(M.key_chir, w);
-        const uint64_t base_frc = word_base(M.key_force, w);
-        const int y0 = (int)(b * T);
+        // single-lattice blocked kernel, with rows counted relative to the
+        // band (d = row - y0, the same for every lane of the item).
+        const uint32_t H = uni(M->H);
+        const uint32_t first = lane - w;  // the band's first lane
+        const uint32_t wl = valid ? first + (w ? w - 1 : wd - 1) : lane;
+        const uint32_t wr = valid ? first + ((w + 1 == wd) ? 0 : w + 1) : lane;
+        const uint32_t cur = (uni(M->cur) + p) & 1;
+        const uint64_t* in = (const uint64_t*)uni((uint64_t)M->buf[cur]);
+        uint64_t* out = (uint64_t*)uni((uint64_t)M->buf[cur ^ 1]);
+        const uint64_t* S = MASK ? (const uint64_t*)uni((uint64_t)M->S) : nullptr;
+        const uint64_t ps = uni(M->ps);
+        const bool walls = uni(M->walls) != 0;
+        const uint64_t tp = uni(M->t0) + (uint64_t)p * K;
+        const uint32_t chi_and32 = uni(M->chi_and), chi_or32 = uni(M->chi_or);
+        const uint64_t chi_and = ((uint64_t)chi_and32 << 32) | chi_and32;
+        const uint64_t chi_or = ((uint64_t)chi_or32 << 32) | chi_or32;
+        const uint64_t thr = uni(M->thr_force);
+        const bool top = b == 0, bot = b + 1 == nb;  // bands whose halos wrap
+        const uint32_t y0 = b * T;
+        // hash states of row y0 at time tp; row y0 + d at time tp + l - 1 adds
+        // the uniform ((l - 1) 2^40 + d 2^20) gamma, and (H 2^20) gamma when
+        // the row wraps
+        const uint64_t R0 = row_term(tp, y0);
+        const uint64_t zc0 = word_base(uni(M->key_chir), w) + R0;
+        const uint64_t zf0 = word_base(uni(M->key_force), w) + R0;
+        const uint64_t HG = row_term(0, H);
+        const uint32_t base_off = y0 * wd + w;  // word offset of row y0 (planes < 2^29 words)
         const int n_iter = (int)T + 2 * K;
 
-        auto wrap_row = [&](int r) __attribute__((always_inline)) -> uint32_t {
-            // r lies in [-K, H + K) and K <= H
-            return (uint32_t)(r < 0 ? r + (int)H : (r >= (int)H ? r - (int)H : r));
+        // Word offset of row y0 + d, wrapped into [0, H).
+        auto row_off = [&](int d) __attribute__((always_inline)) -> uint32_t {
+            uint32_t off = base_off + (uint32_t)(d * (int)wd);
+            if (d < 0) off += top ? H * wd : 0u;
+            else if (d >= (int)T) off -= bot ? H * wd : 0u;
+            return off;
         };
-        auto load = [&](uint32_t y, Row& x) __attribute__((always_inline)) {
-            const size_t off = (size_t)y * wd + w;
+        auto load = [&](int d, Row& x) __attribute__((always_inline)) {
+            const uint32_t boff = row_off(d) * 8u;
 #pragma unroll
-            for (int c = 0; c < 7; c++) x.p[c] = in[c * ps + off];
-            if (MASK) x.s = S ? S[off] : 0ull;
+            for (int c = 0; c < 7; c++) x.p[c] = *(const uint64_t*)((const char*)(in + c * ps) + boff);
+            if (MASK) x.s = S ? *(const uint64_t*)((const char*)S + boff) : 0ull;
         };
 
         uint64_t a3[K + 1], a4[K + 1], bp[K + 1][7], bs[K + 1];
@@ -173,17 +198,21 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
             bc[l] = x.c;
         };
         Row nxt;
-        load(wrap_row(y0 - K), nxt);
+        load(-K, nxt);
 
         auto body = [&](int i, auto full_c, auto par_c) __attribute__((always_inline)) {
             constexpr bool FULL = decltype(full_c)::value;
             constexpr int PAR = decltype(par_c)::value;
-            const int r = y0 - K + i;
-            const uint32_t y = wrap_row(r);
+            const int d0 = i - K;  // loaded row, relative to y0
             Row X = nxt;
-            load((i + 1 < n_iter) ? wrap_row(r + 1) : y, nxt);
+            load((i + 1 < n_iter) ? d0 + 1 : d0, nxt);
             uint64_t s = MASK ? X.s : 0ull;
-            if (walls && (y == 0 || y == H - 1)) s = ~0ull;
+            // wall rows 0 and H-1: rows y0 + d0 in {0, -1} of the first band
+            // and {T - 1, T} of the last
+            if (walls) {
+                if (d0 == 0 || d0 == -1) s = top ? ~0ull : s;
+                else if (d0 == (int)T - 1 || d0 == (int)T) s = bot ? ~0ull : s;
+            }
             X.s = s;
             exchange(xch, slot, nt, lane, wl, wr, X);
             bool have = true;
@@ -197,14 +226,25 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
                         return;
                     }
                 }
-                const uint32_t rho = wrap_row(r - l);
-                constexpr bool odd = ((PAR + K + l) & 1) != 0;  // y0 even: parity of rho
+                const int dl = d0 - l;  // row of this level, relative to y0
+                constexpr bool odd = ((PAR + K + l) & 1) != 0;  // y0 even: parity of the row
                 uint64_t n[7];
                 stream_in<odd>(a3[l], a4[l], ac[l], bp[l], bc[l], X, n);
                 const uint64_t sw = bs[l];
-                const uint64_t R = row_term(tp + (uint64_t)(l - 1), rho);
-                const uint64_t chi = (mix64(base_chi + R) & chi_and) | chi_or;
-                const uint64_t coin = FORCE ? coin_word(mix64(base_frc + R), thr) : 0ull;
+                uint64_t dz = ((uint64_t)(l - 1) << 40) + ((uint64_t)(int64_t)dl << 20);
+                dz *= kGamma;
+                uint64_t zc = zc0 + dz, zf = zf0 + dz;
+                if (dl < 0) {
+                    const uint64_t fix = top ? HG : 0ull;
+                    zc += fix;
+                    zf += fix;
+                } else if (dl >= (int)T) {
+                    const uint64_t fix = bot ? HG : 0ull;
+                    zc -= fix;
+                    zf -= fix;
+                }
+                const uint64_t chi = (mix64(zc) & chi_and) | chi_or;
+                const uint64_t coin = FORCE ? coin_word(mix64(zf), thr) : 0ull;
                 Row Y;
                 update(n, sw, chi, coin, Y.p);
                 Y.s = sw;
@@ -213,9 +253,9 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
                     exchange(xch, slot, nt, lane, wl, wr, Y);
                     X = Y;
                 } else if (active) {
-                    const size_t off = (size_t)rho * wd + w;
+                    const uint32_t boff = (base_off + (uint32_t)(dl * (int)wd)) * 8u;  // 0 <= dl < T
 #pragma unroll
-                    for (int c = 0; c < 7; c++) out[c * ps + off] = Y.p[c];
+                    for (int c = 0; c < 7; c++) *(uint64_t*)((char*)(out + c * ps) + boff) = Y.p[c];
                 }
             });
         };
@@ -239,7 +279,7 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();
             if (active && w == 0)
-                __hip_atomic_fetch_add(done + M.done_off + b, 1u, __ATOMIC_RELEASE,
+                __hip_atomic_fetch_add(done + done_off + b, 1u, __ATOMIC_RELEASE,
                                        __HIP_MEMORY_SCOPE_AGENT);
         }
     }
@@ -280,16 +320,15 @@ __global__ void k_batch_header(BatchHeader* hdr, uint32_t passes, uint32_t K) {
 
 template <int K, bool FORCE, bool MASK>
 hipError_t launch_batch_t(BatchHeader* hdr, MemberDesc* members, const GroupDesc* groups,
-                          const uint32_t* seg_member, const uint32_t* seg_band, uint32_t* done,
-                          uint32_t grid, uint32_t nt, hipStream_t st) {
+                          const WaveDesc* waves, uint32_t* done, uint32_t grid, uint32_t nt,
+                          hipStream_t st) {
     hipLaunchKernelGGL((k_batch<K, FORCE, MASK>), dim3(grid), dim3(nt),
-                       (2 * nt + 1) * sizeof(uint32_t), st, hdr, members, groups, seg_member,
-                       seg_band, done);
+                       (2 * nt + 1) * sizeof(uint32_t), st, hdr, members, groups, waves, done);
     return hipGetLastError();
 }
 
-using BatchLaunch = hipError_t (*)(BatchHeader*, MemberDesc*, const GroupDesc*, const uint32_t*,
-                                   const uint32_t*, uint32_t*, uint32_t, uint32_t, hipStream_t);
+using BatchLaunch = hipError_t (*)(BatchHeader*, MemberDesc*, const GroupDesc*, const WaveDesc*,
+                                   uint32_t*, uint32_t, uint32_t, hipStream_t);
 using BatchKernel = const void*;
 
 template <int K>
@@ -346,8 +385,7 @@ struct Engine {
     BatchHeader* hdr = nullptr;
     MemberDesc* members = nullptr;
     GroupDesc* groups = nullptr;
-    uint32_t* seg_member = nullptr;
-    uint32_t* seg_band = nullptr;
+    WaveDesc* waves = nullptr;
     uint32_t* done = nullptr;
     uint32_t max_members = 0, max_segs = 0;
     // tiling
@@ -366,11 +404,13 @@ struct Engine {
     bool g_force = false, g_mask = false;
 };
 
-// Device table space for up to `members` lattices and `segs` bands.
+// Device table space for up to `members` lattices and `segs` bands: header,
+// members, groups (at most one per band), waves and per-band counters.
 size_t engine_table_words(uint32_t members, uint32_t segs) {
     const size_t w = sizeof(uint64_t);
     return round_up(sizeof(BatchHeader), 256) / w + round_up((size_t)members * sizeof(MemberDesc), 256) / w +
-           round_up((size_t)segs * sizeof(GroupDesc), 256) / w + 3 * (round_up((size_t)segs * 4, 256) / w);
+           round_up((size_t)segs * sizeof(GroupDesc), 256) / w +
+           round_up(max_waves(segs) * sizeof(WaveDesc), 256) / w + round_up((size_t)segs * 4, 256) / w;
 }
 
 int engine_init(Engine* e, uint64_t* tables, uint32_t members, uint32_t segs, hipStream_t st) {
@@ -382,16 +422,14 @@ int engine_init(Engine* e, uint64_t* tables, uint32_t members, uint32_t segs, hi
     p += round_up((size_t)members * sizeof(MemberDesc), 256) / w;
     e->groups = (GroupDesc*)p;
     p += round_up((size_t)segs * sizeof(GroupDesc), 256) / w;
-    e->seg_member = (uint32_t*)p;
-    p += round_up((size_t)segs * 4, 256) / w;
-    e->seg_band = (uint32_t*)p;
-    p += round_up((size_t)segs * 4, 256) / w;
+    e->waves = (WaveDesc*)p;
+    p += round_up(max_waves(segs) * sizeof(WaveDesc), 256) / w;
     e->done = (uint32_t*)p;
     e->max_members = members;
     e->max_segs = segs;
     e->st = st;
     e->stage_bytes = sizeof(BatchHeader) + (size_t)members * sizeof(MemberDesc) +
-                     (size_t)segs * (sizeof(GroupDesc) + 8);
+                     (size_t)segs * sizeof(GroupDesc) + max_waves(segs) * sizeof(WaveDesc);
     FHP_HIP_TRY(hipHostMalloc((void**)&e->stage, e->stage_bytes, hipHostMallocDefault), "pinned");
     FHP_HIP_TRY(hipEventCreateWithFlags(&e->staged, hipEventDisableTiming), "event");
     FHP_HIP_TRY(launch_fill_u64((uint64_t*)e->done, (segs + 1) / 2, 0, st), "clear");
@@ -431,8 +469,6 @@ MemberDesc member_desc(const fhp_sim* s, uint32_t passes, uint32_t T, uint32_t d
     return M;
 }
 
-int engine_grid(uint32_t K, bool force, bool mask, uint32_t nt, uint32_t* grid);
-
 // Builds the member and group tables of sims[0..n) (pass limits `limit`, or
 // no limit) and enqueues their upload on the engine's stream.
 int engine_build(Engine* e, fhp_sim* const* sims, const uint32_t* limit, uint32_t n) {
@@ -451,36 +487,30 @@ int engine_build(Engine* e, fhp_sim* const* sims, const uint32_t* limit, uint32_
         force |= s->D.thr_force != 0;
         mask |= s->has_mask != 0;
     }
-    // bands of equal (wd, H, T) share a workgroup: order the members by that
-    // class, larger work first, and list their bands in that order
+    if (done > e->max_segs) return fail(FHP_E_NOMEM, "%u bands, room for %u", done, e->max_segs);
+    // bands of equal (wd, T) share a workgroup: order the members by that
+    // class, larger work first
     std::sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
         const Lattice &a = sims[x]->L, &b = sims[y]->L;
         if (a.wd != b.wd) return a.wd > b.wd;
-        if (a.H != b.H) return a.H > b.H;
         if (bandT[x] != bandT[y]) return bandT[x] > bandT[y];
-        if (a.ps != b.ps) return a.ps > b.ps;
+        if (a.H != b.H) return a.H > b.H;
         return x < y;
     });
-    std::vector<BandSeg> segs;
-    segs.reserve(done);
-    for (uint32_t i : order)
-        for (uint32_t k = 0; k < mem[i].nbands; k++)
-            segs.push_back({sims[i]->L.wd, bandT[i], sims[i]->L.H, i, k, (uint64_t)sims[i]->L.ps});
-    if (segs.size() > e->max_segs)
-        return fail(FHP_E_NOMEM, "%zu bands, room for %u", segs.size(), e->max_segs);
+    std::vector<MemberBands> mb;
+    mb.reserve(n);
+    for (uint32_t i : order) mb.push_back({i, sims[i]->L.wd, bandT[i], mem[i].nbands});
     uint32_t nt = e->nt_req ? e->nt_req : 64;
     const uint32_t need = (max_wd + 63) / 64 * 64;
     if (nt < need) nt = need;
-    uint32_t grid = 0;
-    if (n) {
-        const int rc = engine_grid(e->depth, force, mask, nt, &grid);
-        if (rc) return rc;
-    }
     std::vector<GroupDesc> groups;
-    std::vector<uint32_t> sm(segs.size()), sb(segs.size());
-    pack_groups(segs, nt, groups, sm.data(), sb.data());
-    split_last_round(groups, nt, grid);
-    order_groups(groups, nt);
+    std::vector<WaveDesc> waves;
+    std::vector<uint32_t> lanes;
+    pack_waves(mb, nt, groups, waves, lanes);
+    order_groups(groups, lanes);
+    if (waves.size() > max_waves(e->max_segs))
+        return fail(FHP_E_NOMEM, "%zu waves, room for %llu", waves.size(),
+                    (unsigned long long)max_waves(e->max_segs));
     BatchHeader h;
     memset(&h, 0, sizeof(h));
     h.n_groups = (uint32_t)groups.size();
@@ -490,19 +520,15 @@ int engine_build(Engine* e, fhp_sim* const* sims, const uint32_t* limit, uint32_
     FHP_HIP_TRY(hipEventSynchronize(e->staged), "event");
     uint8_t* p = e->stage;
     const size_t bh = sizeof(h), bm = mem.size() * sizeof(MemberDesc),
-                 bg = groups.size() * sizeof(GroupDesc), bs = segs.size() * 4;
+                 bg = groups.size() * sizeof(GroupDesc), bw = waves.size() * sizeof(WaveDesc);
     memcpy(p, &h, bh);
     memcpy(p + bh, mem.data(), bm);
     memcpy(p + bh + bm, groups.data(), bg);
-    memcpy(p + bh + bm + bg, sm.data(), bs);
-    memcpy(p + bh + bm + bg + bs, sb.data(), bs);
+    memcpy(p + bh + bm + bg, waves.data(), bw);
     FHP_HIP_TRY(hipMemcpyAsync(e->hdr, p, bh, hipMemcpyHostToDevice, e->st), "upload");
     if (bm) FHP_HIP_TRY(hipMemcpyAsync(e->members, p + bh, bm, hipMemcpyHostToDevice, e->st), "upload");
     if (bg) FHP_HIP_TRY(hipMemcpyAsync(e->groups, p + bh + bm, bg, hipMemcpyHostToDevice, e->st), "upload");
-    if (bs) {
-        FHP_HIP_TRY(hipMemcpyAsync(e->seg_member, p + bh + bm + bg, bs, hipMemcpyHostToDevice, e->st), "upload");
-        FHP_HIP_TRY(hipMemcpyAsync(e->seg_band, p + bh + bm + bg + bs, bs, hipMemcpyHostToDevice, e->st), "upload");
-    }
+    if (bw) FHP_HIP_TRY(hipMemcpyAsync(e->waves, p + bh + bm + bg, bw, hipMemcpyHostToDevice, e->st), "upload");
     FHP_HIP_TRY(hipEventRecord(e->staged, e->st), "event");
     if (done > e->n_done)  // counters beyond the previous tables may be stale
         FHP_HIP_TRY(launch_fill_u64((uint64_t*)e->done, (done + 1) / 2, 0, e->st), "clear");
@@ -544,8 +570,8 @@ int engine_enqueue(Engine* e, uint32_t K, uint32_t passes, uint32_t launches) {
     hipLaunchKernelGGL(k_batch_header, dim3(1), dim3(1), 0, e->st, e->hdr, passes, K);
     FHP_HIP_TRY(hipGetLastError(), "launch");
     for (uint32_t k = 0; k < launches; k++)
-        FHP_HIP_TRY(fn(e->hdr, e->members, e->groups, e->seg_member, e->seg_band, e->done, grid,
-                       e->nt, e->st), "launch");
+        FHP_HIP_TRY(fn(e->hdr, e->members, e->groups, e->waves, e->done, grid, e->nt, e->st),
+                    "launch");
     return FHP_OK;
 }
 

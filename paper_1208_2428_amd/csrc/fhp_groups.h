@@ -2,9 +2,12 @@
 // the batch kernel (plain C++: also built on the host alone to be checked).
 //
 // A band is T consecutive rows of one lattice over its full width (wd 64-node
-// words).  Bands of lattices with the same width, height, band height and
-// plane stride share a workgroup of nt threads, nt / wd of them side by side;
-// the persistent grid takes the resulting items from one queue.
+// words, one lane per word).  A work item is one workgroup of nt lanes; all
+// its bands share wd and T, so every wave of the item sweeps the same rows in
+// lockstep.  Each wave holds bands of a single lattice (a run of consecutive
+// bands that starts on a wave boundary, possibly spanning several waves), so
+// that every per-lattice value -- buffers, keys, time, walls, forcing -- is
+// uniform across the wave and lives in scalar registers.
 #pragma once
 
 #include <stdint.h>
@@ -14,83 +17,87 @@
 
 namespace fhp {
 
+// One item: waves [first_wave, first_wave + nwaves) of the wave table; the
+// workgroup's remaining waves idle.
 struct GroupDesc {
-    uint32_t first, nseg, wd, T, H, pad;
-    uint64_t ps;  // plane stride in words
+    uint32_t wd, T;
+    uint32_t first_wave, nwaves;
 };
 
-struct BandSeg {
-    uint32_t wd, T, H, m, band;
-    uint64_t ps;
+// One wave of an item: lanes of bands band0 .. band0 + count - 1 of member m,
+// laid side by side from the run's first lane; rel0 = lanes of the run that
+// precede this wave's lane 0 (a multiple of 64).
+struct WaveDesc {
+    uint32_t m, band0, count, rel0;
 };
 
-inline bool same_class(const BandSeg& a, const BandSeg& b) {
-    return a.wd == b.wd && a.T == b.T && a.H == b.H && a.ps == b.ps;
-}
+// A member's bands, in the order the members are packed.
+struct MemberBands {
+    uint32_t m, wd, T, nbands;
+};
 
-inline uint64_t group_work(const GroupDesc& g) { return (uint64_t)g.nseg * g.wd * g.T; }
+// Upper bound on the wave-table entries for `bands` bands of at most 512
+// words: a run of c bands of width wd spans ceil(c wd / 64) <= c wd / 64 + 1
+// waves, and there are at most `bands` runs.
+inline uint64_t max_waves(uint64_t bands) { return bands * 9; }
 
-// Packs segs (listed class by class) into groups of at most nt / wd bands;
-// sm / sb receive each segment's member and band in the same order.
-inline void pack_groups(const std::vector<BandSeg>& segs, uint32_t nt, std::vector<GroupDesc>& groups,
-                        uint32_t* sm, uint32_t* sb) {
+// Packs the bands of `mem` (listed class by class, a class being equal
+// (wd, T)) into items of nt lanes.  Appends to groups / waves and returns the
+// lanes holding a band in each group via `lanes` (same length as groups).
+inline void pack_waves(const std::vector<MemberBands>& mem, uint32_t nt,
+                       std::vector<GroupDesc>& groups, std::vector<WaveDesc>& waves,
+                       std::vector<uint32_t>& lanes) {
     groups.clear();
-    for (size_t k = 0; k < segs.size();) {
-        GroupDesc g{};
-        g.first = (uint32_t)k;
-        g.wd = segs[k].wd;
-        g.T = segs[k].T;
-        g.H = segs[k].H;
-        g.ps = segs[k].ps;
-        const uint32_t cap = nt / g.wd;
-        const size_t k0 = k;
-        while (k < segs.size() && g.nseg < cap && same_class(segs[k], segs[k0])) {
-            sm[k] = segs[k].m;
-            sb[k] = segs[k].band;
-            g.nseg++;
-            k++;
+    waves.clear();
+    lanes.clear();
+    bool open = false;
+    GroupDesc g{};
+    uint32_t pos = 0, used = 0;  // next free lane (a wave boundary), lanes holding bands
+    auto close = [&]() {
+        if (open && g.nwaves) {
+            groups.push_back(g);
+            lanes.push_back(used);
         }
-        groups.push_back(g);
+        open = false;
+    };
+    for (const MemberBands& mb : mem) {
+        if (open && (g.wd != mb.wd || g.T != mb.T)) close();
+        uint32_t b = 0;
+        while (b < mb.nbands) {
+            if (!open) {
+                g = GroupDesc{mb.wd, mb.T, (uint32_t)waves.size(), 0};
+                pos = used = 0;
+                open = true;
+            }
+            const uint32_t fit = (nt - pos) / mb.wd;
+            if (fit == 0) {
+                close();
+                continue;
+            }
+            const uint32_t cnt = std::min(mb.nbands - b, fit);
+            const uint32_t nw = (cnt * mb.wd + 63) / 64;
+            for (uint32_t k = 0; k < nw; k++) waves.push_back({mb.m, b, cnt, 64 * k});
+            g.nwaves += nw;
+            pos += 64 * nw;
+            used += cnt * mb.wd;
+            b += cnt;
+            if (pos >= nt) close();
+        }
     }
+    close();
 }
 
-// When a pass has a few full rounds of items on the persistent grid plus a
-// part-filled last one, most of the grid idles while that last round runs.
-// The groups that would make it up (the largest, which run first) are split
-// into one-wave pieces, which run last and spread that work over the whole
-// grid.  Segments stay consecutive, so only the group table changes.
-inline void split_last_round(std::vector<GroupDesc>& groups, uint32_t nt, uint32_t grid) {
-    const size_t G = groups.size();
-    if (!grid || G <= grid || G % grid == 0 || nt <= 64) return;
-    const size_t rem = G % grid;
-    std::vector<size_t> idx(G);
-    for (size_t k = 0; k < G; k++) idx[k] = k;
-    std::nth_element(idx.begin(), idx.begin() + (rem - 1), idx.end(),
-                     [&](size_t x, size_t y) { return group_work(groups[x]) > group_work(groups[y]); });
-    std::vector<GroupDesc> pieces;
-    for (size_t r = 0; r < rem; r++) {
-        GroupDesc& g = groups[idx[r]];
-        const uint32_t per = g.wd >= 64 ? 1u : 64u / g.wd;  // bands in one wave's worth
-        if (g.nseg <= per) continue;
-        for (uint32_t k = per; k < g.nseg; k += per) {
-            GroupDesc q = g;
-            q.first = g.first + k;
-            q.nseg = g.nseg - k < per ? g.nseg - k : per;
-            pieces.push_back(q);
-        }
-        g.nseg = per;
-    }
-    groups.insert(groups.end(), pieces.begin(), pieces.end());
-}
-
-// Queue order, largest work first: full groups in their class order ahead of
-// the few part-filled ones, which are sorted among themselves.
-inline void order_groups(std::vector<GroupDesc>& groups, uint32_t nt) {
-    auto part = std::stable_partition(groups.begin(), groups.end(),
-                                      [&](const GroupDesc& g) { return g.nseg == nt / g.wd; });
-    std::stable_sort(part, groups.end(), [](const GroupDesc& x, const GroupDesc& y) {
-        return group_work(x) > group_work(y);
+// Queue order: most lanes x rows first (stable, so classes keep their order
+// among equals).
+inline void order_groups(std::vector<GroupDesc>& groups, const std::vector<uint32_t>& lanes) {
+    std::vector<uint32_t> idx(groups.size());
+    for (uint32_t k = 0; k < idx.size(); k++) idx[k] = k;
+    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) {
+        return (uint64_t)lanes[x] * groups[x].T > (uint64_t)lanes[y] * groups[y].T;
     });
+    std::vector<GroupDesc> out(groups.size());
+    for (uint32_t k = 0; k < idx.size(); k++) out[k] = groups[idx[k]];
+    groups.swap(out);
 }
 
 }  // namespace fhp

@@ -1,12 +1,15 @@
 // Host check of the batch engine's packing of bands into workgroup items
-// (fhp_groups.h): every band is in exactly one item, an item holds bands of
-// one class that fit its workgroup, the last round of a pass is split into
-// one-wave pieces, and the queue runs full items first, then the rest by
-// decreasing work.  Prints OK on success.
+// (fhp_groups.h): every band of every member is in exactly one item; an item
+// holds bands of one (wd, T) class that fit its workgroup; every wave holds
+// bands of a single member; the lane -> band mapping that the kernel derives
+// from a wave's descriptor gives each band wd lanes inside the workgroup; and
+// the queue runs items by decreasing lanes x rows.  Prints OK on success.
 #include <stdio.h>
 #include <stdlib.h>
 
+#include <map>
 #include <random>
+#include <utility>
 #include <vector>
 
 #include "fhp_groups.h"
@@ -25,116 +28,122 @@ static int fails = 0;
         }                                          \
     } while (0)
 
-struct Mem {
-    uint32_t wd, H, T;
-    uint64_t ps;
-};
-
-static void check_case(const std::vector<Mem>& mem, uint32_t nt, uint32_t grid, int id) {
-    // list bands class by class, as the engine does after sorting its members
-    std::vector<uint32_t> order(mem.size());
-    for (uint32_t i = 0; i < mem.size(); i++) order[i] = i;
-    std::sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
-        const Mem &a = mem[x], &b = mem[y];
-        if (a.wd != b.wd) return a.wd > b.wd;
-        if (a.H != b.H) return a.H > b.H;
-        if (a.T != b.T) return a.T > b.T;
-        if (a.ps != b.ps) return a.ps > b.ps;
-        return x < y;
-    });
-    std::vector<BandSeg> segs;
-    for (uint32_t i : order)
-        for (uint32_t b = 0; b < mem[i].H / mem[i].T; b++)
-            segs.push_back({mem[i].wd, mem[i].T, mem[i].H, i, b, mem[i].ps});
+static void check_case(const std::vector<MemberBands>& mem, uint32_t nt, int id) {
     std::vector<GroupDesc> groups;
-    std::vector<uint32_t> sm(segs.size()), sb(segs.size());
-    pack_groups(segs, nt, groups, sm.data(), sb.data());
-    const size_t G0 = groups.size();
-    size_t unsplittable = 0;  // groups of one wave or less cannot be split
-    for (const GroupDesc& g : groups) unsplittable += g.nseg <= (g.wd >= 64 ? 1u : 64u / g.wd);
-    split_last_round(groups, nt, grid);
-    order_groups(groups, nt);
+    std::vector<WaveDesc> waves;
+    std::vector<uint32_t> lanes;
+    pack_waves(mem, nt, groups, waves, lanes);
+    CHECK(groups.size() == lanes.size(), "case %d lanes table", id);
+    // lanes per group before ordering, keyed by first wave (unique per group)
+    std::map<uint32_t, uint32_t> used_of;
+    for (size_t g = 0; g < groups.size(); g++) used_of[groups[g].first_wave] = lanes[g];
+    order_groups(groups, lanes);
 
-    std::vector<int> seen(segs.size(), 0);
-    for (size_t k = 0; k < segs.size(); k++) {
-        CHECK(sm[k] == segs[k].m && sb[k] == segs[k].band, "case %d seg %zu tables", id, k);
+    uint64_t total_bands = 0, total_lanes = 0;
+    std::map<uint32_t, const MemberBands*> by_m;
+    for (const MemberBands& mb : mem) {
+        by_m[mb.m] = &mb;
+        total_bands += mb.nbands;
+        total_lanes += (uint64_t)mb.nbands * mb.wd;
     }
-    for (size_t j = 0; j < groups.size(); j++) {
-        const GroupDesc& g = groups[j];
-        CHECK(g.nseg >= 1 && g.nseg * g.wd <= nt, "case %d group %zu nseg %u wd %u nt %u", id, j,
-              g.nseg, g.wd, nt);
-        CHECK(g.first + g.nseg <= segs.size(), "case %d group %zu range", id, j);
-        for (uint32_t k = g.first; k < g.first + g.nseg && k < segs.size(); k++) {
-            seen[k]++;
-            const BandSeg& s = segs[k];
-            CHECK(s.wd == g.wd && s.T == g.T && s.H == g.H && s.ps == g.ps,
-                  "case %d group %zu mixes classes", id, j);
+    CHECK(waves.size() <= max_waves(total_bands), "case %d: %zu waves > bound", id, waves.size());
+    std::map<std::pair<uint32_t, uint32_t>, int> seen;  // (member, band) -> count
+    uint64_t prev_work = ~0ull;
+    for (size_t g = 0; g < groups.size(); g++) {
+        const GroupDesc& G = groups[g];
+        CHECK(G.nwaves >= 1 && G.nwaves * 64 <= nt, "case %d group %zu nwaves %u", id, g, G.nwaves);
+        CHECK(G.first_wave + G.nwaves <= waves.size(), "case %d group %zu range", id, g);
+        // the kernel's lane mapping, lane by lane
+        std::map<std::pair<uint32_t, uint32_t>, uint32_t> lanes_of_band;
+        uint32_t used = 0;
+        for (uint32_t lane = 0; lane < nt; lane++) {
+            const uint32_t wave = lane / 64;
+            if (wave >= G.nwaves) continue;
+            const WaveDesc& D = waves[G.first_wave + wave];
+            const MemberBands* mb = by_m.count(D.m) ? by_m[D.m] : nullptr;
+            CHECK(mb != nullptr, "case %d unknown member %u", id, D.m);
+            if (!mb) continue;
+            CHECK(mb->wd == G.wd && mb->T == G.T, "case %d group %zu mixes classes", id, g);
+            CHECK(D.rel0 % 64 == 0, "case %d rel0 %u", id, D.rel0);
+            const uint32_t rel = D.rel0 + (lane & 63);
+            const uint32_t j = rel / G.wd, w = rel - j * G.wd;
+            if (j >= D.count) continue;
+            const uint32_t b = D.band0 + j;
+            CHECK(b < mb->nbands, "case %d band %u of %u", id, b, mb->nbands);
+            const uint32_t first = lane - w;
+            CHECK(first + G.wd <= nt, "case %d band lanes leave the workgroup", id);
+            // every lane of the band is in a wave of the same run
+            for (uint32_t q = first; q < first + G.wd && q < nt; q++) {
+                const uint32_t wq = q / 64;
+                CHECK(wq < G.nwaves, "case %d band lane %u in an idle wave", id, q);
+                if (wq >= G.nwaves) continue;
+                const WaveDesc& E = waves[G.first_wave + wq];
+                CHECK(E.m == D.m && E.band0 == D.band0 && E.count == D.count &&
+                          E.rel0 - D.rel0 == 64 * (wq - wave),
+                      "case %d band straddles runs", id);
+            }
+            lanes_of_band[{D.m, b}]++;
+            used++;
         }
+        for (auto& kv : lanes_of_band) {
+            CHECK(kv.second == G.wd, "case %d member %u band %u has %u lanes", id, kv.first.first,
+                  kv.first.second, kv.second);
+            seen[kv.first]++;
+        }
+        CHECK(used_of.count(G.first_wave) && used_of[G.first_wave] == used,
+              "case %d group %zu lane count", id, g);
+        const uint64_t work = (uint64_t)used * G.T;
+        CHECK(work <= prev_work, "case %d queue order at %zu", id, g);
+        prev_work = work;
+        total_lanes -= used;
     }
-    for (size_t k = 0; k < segs.size(); k++)
-        CHECK(seen[k] == 1, "case %d seg %zu covered %d times", id, k, seen[k]);
-    // queue order: full groups, then part-filled ones by decreasing work
-    size_t nfull = 0;
-    while (nfull < groups.size() && groups[nfull].nseg == nt / groups[nfull].wd) nfull++;
-    for (size_t j = nfull; j < groups.size(); j++) {
-        CHECK(groups[j].nseg < nt / groups[j].wd, "case %d full group %zu after a part-filled one",
-              id, j);
-        if (j > nfull)
-            CHECK(group_work(groups[j - 1]) >= group_work(groups[j]), "case %d order at %zu", id, j);
-    }
-    // the last round: with rem = G0 mod grid groups in it, the rem largest
-    // are split, so at most G0 - rem + unsplittable full-size groups remain
-    if (grid && G0 > grid && G0 % grid && nt > 64) {
-        const size_t rem = G0 % grid;
-        CHECK(nfull <= G0 - rem + unsplittable, "case %d: %zu full groups of %zu, last round %zu",
-              id, nfull, G0, rem);
-        CHECK(groups.size() >= G0, "case %d lost groups", id);
-    } else {
-        CHECK(groups.size() == G0, "case %d split without a last round", id);
-    }
+    CHECK(total_lanes == 0, "case %d lanes left over", id);
+    for (const MemberBands& mb : mem)
+        for (uint32_t b = 0; b < mb.nbands; b++) {
+            const int k = seen[std::make_pair(mb.m, b)];
+            CHECK(k == 1, "case %d member %u band %u covered %d times", id, mb.m, b, k);
+        }
 }
 
 int main() {
     std::mt19937_64 rng(12345);
     int id = 0;
-    // one class, every group full except the last: the split leaves exactly
-    // whole rounds of full groups
+    // small lattices packed many to a wave, one member per wave
     {
-        std::vector<Mem> mem;
-        for (int i = 0; i < 100; i++) mem.push_back({8, 256, 32, 8 * 256});
-        const uint32_t nt = 256, grid = 64;  // 800 bands, 32 per group -> 25 groups
-        check_case(mem, nt, grid, id++);
-        check_case(mem, nt, 16, id++);       // 25 = 16 + 9
-        std::vector<BandSeg> segs;
-        for (uint32_t i = 0; i < mem.size(); i++)
-            for (uint32_t b = 0; b < 8; b++) segs.push_back({8, 32, 256, i, b, 8 * 256});
+        std::vector<MemberBands> mem;
+        for (uint32_t i = 0; i < 10; i++) mem.push_back({i, 2, 32, 4});  // 8 lanes each
+        check_case(mem, 256, id++);
         std::vector<GroupDesc> g;
-        std::vector<uint32_t> sm(segs.size()), sb(segs.size());
-        pack_groups(segs, nt, g, sm.data(), sb.data());
-        CHECK(g.size() == 25, "groups %zu", g.size());
-        split_last_round(g, nt, 16);
-        order_groups(g, nt);
-        size_t full = 0;
-        for (auto& x : g) full += x.nseg == 32;
-        CHECK(full == 16, "full groups after split %zu", full);
-        CHECK(g.size() == 16 + 9 * 4, "pieces %zu", g.size());  // 32 bands -> 4 one-wave pieces
+        std::vector<WaveDesc> w;
+        std::vector<uint32_t> l;
+        pack_waves(mem, 256, g, w, l);
+        CHECK(g.size() == 3 && w.size() == 10, "10 members of 8 lanes: %zu groups %zu waves",
+              g.size(), w.size());  // one wave each, four waves per workgroup
     }
-    // random mixes of widths, heights and band heights
+    // a band wider than a wave spans waves of one run
+    {
+        std::vector<MemberBands> mem = {{0, 100, 16, 5}, {1, 100, 16, 3}};
+        check_case(mem, 256, id++);
+    }
+    // random mixes of widths, band heights and band counts, members listed
+    // class by class as the engine does
     for (int c = 0; c < 300; c++) {
-        const int n = 1 + (int)(rng() % 200);
-        std::vector<Mem> mem;
+        const int n = 1 + (int)(rng() % 120);
+        std::vector<MemberBands> mem;
         uint32_t max_wd = 1;
         for (int i = 0; i < n; i++) {
             const uint32_t wd = 1u + (uint32_t)(rng() % ((c % 3 == 0) ? 512 : 40));
-            const uint32_t T = 2u * (1u + (uint32_t)(rng() % 32));
-            const uint32_t H = T * (1u + (uint32_t)(rng() % 40));
-            mem.push_back({wd, H, T, (uint64_t)wd * H + (rng() % 2) * 32});
+            const uint32_t T = 2u * (1u + (uint32_t)(rng() % 4));
+            mem.push_back({(uint32_t)(1000 + i), wd, T, 1u + (uint32_t)(rng() % 40)});
             max_wd = std::max(max_wd, wd);
         }
+        std::stable_sort(mem.begin(), mem.end(), [](const MemberBands& a, const MemberBands& b) {
+            if (a.wd != b.wd) return a.wd > b.wd;
+            return a.T > b.T;
+        });
         uint32_t nt = 64u << (rng() % 4);
         if (nt < (max_wd + 63) / 64 * 64) nt = (max_wd + 63) / 64 * 64;
-        const uint32_t grid = (uint32_t)(rng() % 3000);
-        check_case(mem, nt, grid, id++);
+        check_case(mem, nt, id++);
     }
     if (fails) {
         printf("%d failures\n", fails);

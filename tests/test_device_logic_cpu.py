@@ -35,8 +35,8 @@ def test_update_matches_oracle_table_exhaustively(checker):
 
 def test_batch_band_packing(tmp_path):
     """Packing of lattice bands into the batch kernel's work items (host code
-    of the batch engine, built with g++): coverage, class purity, fit, the
-    split of a pass's last round and the queue order."""
+    of the batch engine, built with g++): coverage, class purity, one member
+    per wave, the kernel's lane-to-band mapping and the queue order."""
     if not shutil.which("g++"):
         pytest.skip("g++ not available")
     exe = str(tmp_path / "groups_check")
