@@ -11,14 +11,15 @@
 // registers; per lane remain the word, the band and the hash base.  The
 // horizontal carry exchange wraps inside each band's lanes.
 //
-// Work items are (pass, group) pairs taken in pass-major order from a global
-// counter by a persistent grid.  A band's pass p reads its own rows and the K
-// rows on each side, i.e. the neighbouring bands' results of pass p-1, and
-// overwrites the buffer those bands read in pass p-1; so item (p, band b)
-// waits until bands b-1, b, b+1 have completed p passes (agent-scope
-// release/acquire on per-band counters).  Items are taken in order and every
-// taken item is held by a running workgroup, so the oldest unfinished item can
-// always proceed.  The wait is bounded: on time-out the launch aborts and the
+// Work items are (pass, group) pairs in pass-major order: workgroup g takes
+// item g first, later items come from a global counter.  A band's pass p
+// reads its own rows and the K rows on each side, i.e. the neighbouring
+// bands' results of pass p-1, and overwrites the buffer those bands read in
+// pass p-1; so item (p, band b) waits until bands b-1, b, b+1 have completed
+// p passes (agent-scope release/acquire on per-band counters).  Items are
+// taken in order and every taken item is held by a running workgroup (the
+// grid is never larger than what is resident at once), so the oldest
+// unfinished item can always proceed.  The wait is bounded: on time-out the launch aborts and the
 // host reports an error.  The last workgroup to leave advances every member's
 // time and buffer index and resets the counters, so a launch can be replayed
 // from a graph without host work in between.
@@ -88,11 +89,19 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
     const uint32_t n_items = n_groups * passes;
     uint32_t slot = 0;
 
+    bool first = true;
     for (;;) {
-        if (lane == 0) bcast[0] = atomicAdd(&hdr->queue, 1u);
-        __syncthreads();
-        const uint32_t item = uni(bcast[0]);
-        __syncthreads();
+        uint32_t item;
+        if (first) {  // the first round of items is static: item = workgroup
+            item = blockIdx.x;
+            first = false;
+        } else {
+            if (n_items <= gridDim.x) break;
+            if (lane == 0) bcast[0] = atomicAdd(&hdr->queue, 1u) + gridDim.x;
+            __syncthreads();
+            item = uni(bcast[0]);
+            __syncthreads();
+        }
         if (item >= n_items) break;
         const uint32_t p = item / n_groups;
         const GroupDesc G = groups[item - p * n_groups];
@@ -285,14 +294,18 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
     }
 
     // The last workgroup out advances the members and resets the counters.
+    // With one pass per launch no workgroup reads what another wrote (the
+    // member table is only read until a workgroup leaves, and the kernel
+    // boundary publishes the rest), so the exit needs no agent-scope fence:
+    // an L2 write-back per workgroup cost 13% of such a launch.
     __syncthreads();
     if (lane == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        if (passes > 1) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         bcast[0] = atomicAdd(&hdr->exited, 1u);
     }
     __syncthreads();
     if (bcast[0] == gridDim.x - 1) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (passes > 1) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (hdr->status == 0) {
             for (uint32_t k = lane; k < hdr->n_members; k += nt) {
                 MemberDesc& M = members[k];
