@@ -23,6 +23,7 @@ _LIB_PATH = os.path.join(_HERE, "libfhporacle.so")
 
 CHIR_HASH, CHIR_ZERO, CHIR_ONE = 0, 1, 2
 TAG_INIT, TAG_CHIR, TAG_FORCE = 1, 2, 3
+RULES_FHP2, RULES_FHP1, RULES_FHP3 = 0, 1, 2
 
 _lib = None
 
@@ -53,6 +54,8 @@ def _load():
     lib.fhpo_hash.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     lib.fhpo_collision_table.restype = None
     lib.fhpo_collision_table.argtypes = [ctypes.c_int, u8p]
+    lib.fhpo_rule_table.restype = ctypes.c_int
+    lib.fhpo_rule_table.argtypes = [ctypes.c_int, ctypes.c_int, u8p]
     lib.fhpo_init.restype = ctypes.c_int
     lib.fhpo_init.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
                               ctypes.c_double, u8p, ctypes.c_int, u8p]
@@ -63,6 +66,14 @@ def _load():
     lib.fhpo_run.argtypes = [u8p, u8p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
                              ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, ctypes.c_int,
                              ctypes.c_int, i64p]
+    lib.fhpo_step_rules.restype = ctypes.c_int64
+    lib.fhpo_step_rules.argtypes = [u8p, u8p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                                    ctypes.c_uint64, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_int]
+    lib.fhpo_run_rules.restype = ctypes.c_int
+    lib.fhpo_run_rules.argtypes = [u8p, u8p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                                   ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, ctypes.c_int,
+                                   ctypes.c_int, ctypes.c_int, i64p]
     lib.fhpo_observe_global.restype = None
     lib.fhpo_observe_global.argtypes = [u8p, ctypes.c_uint32, ctypes.c_uint32, i64p]
     lib.fhpo_observe_blocks.restype = ctypes.c_int
@@ -98,6 +109,14 @@ def collision_table(chi: int) -> np.ndarray:
     return out
 
 
+def rule_table(rules: int, chi: int) -> np.ndarray:
+    """Collision table of rule set RULES_FHP2 / RULES_FHP1 / RULES_FHP3."""
+    out = np.zeros(128, dtype=np.uint8)
+    if _load().fhpo_rule_table(int(rules), int(chi), _u8(out)) != 0:
+        raise ValueError("fhpo_rule_table: bad arguments")
+    return out
+
+
 def init(W: int, H: int, seed: int, fill: float, mask: np.ndarray | None = None,
          walls: bool = False) -> np.ndarray:
     state = np.empty((H, W), dtype=np.uint8)
@@ -114,28 +133,28 @@ def init(W: int, H: int, seed: int, fill: float, mask: np.ndarray | None = None,
 
 
 def step(state: np.ndarray, t: int, seed: int, force_rate: float = 0.0,
-         chir_mode: int = CHIR_HASH, threads: int = 1):
+         chir_mode: int = CHIR_HASH, threads: int = 1, rules: int = RULES_FHP2):
     """One step t -> t+1.  Returns (new_state, forcing swaps applied)."""
     _check_state(state)
     H, W = state.shape
     out = np.empty_like(state)
-    r = _load().fhpo_step(_u8(state), _u8(out), W, H, t, seed, float(force_rate),
-                          int(chir_mode), int(threads))
+    r = _load().fhpo_step_rules(_u8(state), _u8(out), W, H, t, seed, float(force_rate),
+                                int(chir_mode), int(rules), int(threads))
     if r < 0:
         raise ValueError("fhpo_step: bad arguments")
     return out, int(r)
 
 
 def run(state: np.ndarray, t0: int, n: int, seed: int, force_rate: float = 0.0,
-        chir_mode: int = CHIR_HASH, threads: int = 1):
+        chir_mode: int = CHIR_HASH, threads: int = 1, rules: int = RULES_FHP2):
     """n steps from time t0.  Returns (new_state, total forcing swaps)."""
     _check_state(state)
     H, W = state.shape
     cur = state.copy()
     tmp = np.empty_like(cur)
     swaps = ctypes.c_int64(0)
-    rc = _load().fhpo_run(_u8(cur), _u8(tmp), W, H, t0, n, seed, float(force_rate),
-                          int(chir_mode), int(threads), ctypes.byref(swaps))
+    rc = _load().fhpo_run_rules(_u8(cur), _u8(tmp), W, H, t0, n, seed, float(force_rate),
+                                int(chir_mode), int(rules), int(threads), ctypes.byref(swaps))
     if rc != 0:
         raise ValueError("fhpo_run: bad arguments")
     return cur, int(swaps.value)

@@ -121,6 +121,73 @@ void fhpo_collision_table(int chi, uint8_t out[128])
     }
 }
 
+/* FHP-I (Frisch, Hasslacher & Pomeau 1986): six moving channels only.  A
+ * head-on pair alone turns by +60 degrees (chi = 1) or -60 degrees (chi = 0);
+ * the symmetric triples {0,2,4} and {1,3,5} exchange.  The rest bit is a
+ * spectator: it never changes and never blocks a collision. */
+static void fhp1_table(int chi, uint8_t out[128])
+{
+    for (int s = 0; s < 128; s++) {
+        int moving = s & 63;
+        int rest = s & 64;
+        int res = s;
+        for (int i = 0; i < 3; i++) {
+            if (moving == (bit(i) | bit(i + 3)))
+                res = (chi ? (bit(i + 1) | bit(i + 4)) : (bit(i - 1) | bit(i + 2))) | rest;
+        }
+        int even = bit(0) | bit(2) | bit(4);
+        int odd = bit(1) | bit(3) | bit(5);
+        if (moving == even) res = odd | rest;
+        if (moving == odd) res = even | rest;
+        out[s] = (uint8_t)res;
+    }
+}
+
+static int mass_of(int s)
+{
+    int m = 0;
+    for (int c = 0; c < 7; c++) m += (s >> c) & 1;
+    return m;
+}
+
+/* FHP-III, collision-saturated: every state that shares its mass and
+ * momentum with another state changes.  Reading used here:
+ *   - states of mass <= 3: FHP-II where FHP-II changes the state; FHP-II
+ *     leaves unchanged, of the states that can change, exactly the six
+ *     three-member classes {A_j, B_j, C_j} (j = 0..5) with
+ *       A_j = {j, j+1, j+4}   (head-on pair j+1, j+4 and spectator j),
+ *       B_j = {j, j+2, j+5}   (the pair turned by +60 degrees),
+ *       C_j = {j+1, j+5} + rest,
+ *     which cycle A -> B -> C -> A for chi = 1 and the other way for chi = 0;
+ *   - states of mass >= 4 follow by particle-hole duality:
+ *     T(s) = ~T(~s) on the seven particle bits. */
+static void fhp3_table(int chi, uint8_t out[128])
+{
+    uint8_t low[128];
+    fhpo_collision_table(chi, low);
+    for (int j = 0; j < 6; j++) {
+        int A = bit(j) | bit(j + 1) | bit(j + 4);
+        int B = bit(j) | bit(j + 2) | bit(j + 5);
+        int C = bit(j + 1) | bit(j + 5) | 64;
+        low[A] = (uint8_t)(chi ? B : C);
+        low[B] = (uint8_t)(chi ? C : A);
+        low[C] = (uint8_t)(chi ? A : B);
+    }
+    for (int s = 0; s < 128; s++)
+        out[s] = mass_of(s) <= 3 ? low[s] : (uint8_t)(~low[~s & 127] & 127);
+}
+
+int fhpo_rule_table(int rules, int chi, uint8_t out[128])
+{
+    if (!out || (chi != 0 && chi != 1)) return -1;
+    switch (rules) {
+        case FHPO_RULES_FHP2: fhpo_collision_table(chi, out); return 0;
+        case FHPO_RULES_FHP1: fhp1_table(chi, out); return 0;
+        case FHPO_RULES_FHP3: fhp3_table(chi, out); return 0;
+        default: return -1;
+    }
+}
+
 /* ---------------------------------------------------------------------- */
 /* Initial state.                                                           */
 
@@ -177,13 +244,20 @@ int64_t fhpo_step(const uint8_t *in, uint8_t *out, uint32_t W, uint32_t H,
                   uint64_t t, uint64_t seed, double force_rate, int chir_mode,
                   int nthreads)
 {
+    return fhpo_step_rules(in, out, W, H, t, seed, force_rate, chir_mode, FHPO_RULES_FHP2,
+                           nthreads);
+}
+
+int64_t fhpo_step_rules(const uint8_t *in, uint8_t *out, uint32_t W, uint32_t H,
+                        uint64_t t, uint64_t seed, double force_rate, int chir_mode,
+                        int rules, int nthreads)
+{
     if (!in || !out || in == out || W == 0 || H == 0 || (H & 1)) return -1;
     if (!(force_rate >= 0.0 && force_rate < 1.0 / 64.0)) return -1;
     if (chir_mode < FHPO_CHIR_HASH || chir_mode > FHPO_CHIR_ONE) return -1;
 
     uint8_t table[2][128];
-    fhpo_collision_table(0, table[0]);
-    fhpo_collision_table(1, table[1]);
+    if (fhpo_rule_table(rules, 0, table[0]) || fhpo_rule_table(rules, 1, table[1])) return -1;
     uint64_t key_chir = key_for(seed, FHPO_TAG_CHIR);
     uint64_t key_force = key_for(seed, FHPO_TAG_FORCE);
     uint64_t thr = (uint64_t)floor(force_rate * 274877906944.0); /* floor(f * 2^38) */
@@ -229,10 +303,19 @@ int fhpo_run(uint8_t *state, uint8_t *tmp, uint32_t W, uint32_t H, uint64_t t0,
              uint64_t n, uint64_t seed, double force_rate, int chir_mode,
              int nthreads, int64_t *swaps)
 {
+    return fhpo_run_rules(state, tmp, W, H, t0, n, seed, force_rate, chir_mode,
+                          FHPO_RULES_FHP2, nthreads, swaps);
+}
+
+int fhpo_run_rules(uint8_t *state, uint8_t *tmp, uint32_t W, uint32_t H, uint64_t t0,
+                   uint64_t n, uint64_t seed, double force_rate, int chir_mode,
+                   int rules, int nthreads, int64_t *swaps)
+{
     int64_t total = 0;
     size_t bytes = (size_t)W * H;
     for (uint64_t k = 0; k < n; k++) {
-        int64_t r = fhpo_step(state, tmp, W, H, t0 + k, seed, force_rate, chir_mode, nthreads);
+        int64_t r = fhpo_step_rules(state, tmp, W, H, t0 + k, seed, force_rate, chir_mode, rules,
+                                    nthreads);
         if (r < 0) return -1;
         total += r;
         memcpy(state, tmp, bytes);

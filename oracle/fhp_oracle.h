@@ -53,9 +53,20 @@ extern "C" {
  * (Steele, Lea & Flood, OOPSLA 2014), i.e. mix(key + (n+1)*gamma) mod 2^64. */
 uint64_t fhpo_hash(uint64_t key, uint64_t n);
 
+/* Rule sets.  The paper's rule figure is missing (Sec. 2); FHP-II is the
+ * reading of its model, FHP-I and the collision-saturated FHP-III are the
+ * variants of the same lattice gas (Frisch et al. 1987). */
+#define FHPO_RULES_FHP2 0
+#define FHPO_RULES_FHP1 1
+#define FHPO_RULES_FHP3 2
+
 /* Collision table T_chi for fluid nodes: out[s] for s = 0..127 (7 particle
  * bits, FHP-II rule set).  chi must be 0 or 1. */
 void fhpo_collision_table(int chi, uint8_t out[128]);
+
+/* Collision table of rule set `rules` (FHPO_RULES_*).  Returns 0, or -1 for an
+ * unknown rule set or chi not in {0, 1}. */
+int fhpo_rule_table(int rules, int chi, uint8_t out[128]);
 
 /* Initial state: fluid node bit c (c = 0..6) is set iff
  * (H(key_init, c*2^40 + y*2^20 + x) >> 32) < floor(fill * 2^32).  Solid nodes
@@ -73,12 +84,22 @@ int64_t fhpo_step(const uint8_t *in, uint8_t *out, uint32_t W, uint32_t H,
                   uint64_t t, uint64_t seed, double force_rate, int chir_mode,
                   int nthreads);
 
+/* fhpo_step with the collision of rule set `rules` (fhpo_step uses FHP-II). */
+int64_t fhpo_step_rules(const uint8_t *in, uint8_t *out, uint32_t W, uint32_t H,
+                        uint64_t t, uint64_t seed, double force_rate, int chir_mode,
+                        int rules, int nthreads);
+
 /* Runs n steps starting at time t0 with two arrays; the final state is left in
  * `state`.  `tmp` is a caller-provided W*H scratch array.  swaps (nullable)
  * receives the total forcing swaps.  Returns 0 or -1. */
 int fhpo_run(uint8_t *state, uint8_t *tmp, uint32_t W, uint32_t H, uint64_t t0,
              uint64_t n, uint64_t seed, double force_rate, int chir_mode,
              int nthreads, int64_t *swaps);
+
+/* fhpo_run with the collision of rule set `rules`. */
+int fhpo_run_rules(uint8_t *state, uint8_t *tmp, uint32_t W, uint32_t H, uint64_t t0,
+                   uint64_t n, uint64_t seed, double force_rate, int chir_mode,
+                   int rules, int nthreads, int64_t *swaps);
 
 /* Global observables, summed over all nodes (solid ones included):
  * out[0] = mass, out[1] = p_x, out[2] = p_y (momentum in units of (1/2,

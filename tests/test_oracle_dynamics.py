@@ -139,7 +139,7 @@ def test_mass_conserved_with_walls_and_obstacles():
 
 
 # ---------------------------------------------------------- inverse dynamics
-def inverse_step(state, t, seed):
+def inverse_step(state, t, seed, rules=oracle.RULES_FHP2):
     """Undoes one forcing-free step: invert the per-node map (table permutation
     for fluid nodes with this node's chirality, bounce-back for solid ones),
     then push every particle back along -c_i."""
@@ -150,7 +150,7 @@ def inverse_step(state, t, seed):
                 (np.uint64(t) << np.uint64(40)) + (ys.astype(np.uint64) << np.uint64(20))
                 + (xs // 64).astype(np.uint64))
     chi = ((h >> (xs % 64).astype(np.uint64)) & np.uint64(1)).astype(np.int64)
-    inv = [np.argsort(oracle.collision_table(c)) for c in (0, 1)]
+    inv = [np.argsort(oracle.rule_table(rules, c)) for c in (0, 1)]
     solid = state >> 7
     low = state & 0x7F
     pre = np.where(chi == 1, inv[1][low], inv[0][low]).astype(np.uint8)
@@ -172,7 +172,8 @@ def inverse_step(state, t, seed):
     return out.astype(np.uint8)
 
 
-def test_inverse_dynamics_recovers_initial_state():
+@pytest.mark.parametrize("rules", [oracle.RULES_FHP2, oracle.RULES_FHP1, oracle.RULES_FHP3])
+def test_inverse_dynamics_recovers_initial_state(rules):
     rng = np.random.default_rng(4)
     W, H = 64, 8
     solid = rng.random((H, W)) < 0.15
@@ -180,9 +181,9 @@ def test_inverse_dynamics_recovers_initial_state():
     s = s0.copy()
     n = 6
     for t in range(n):
-        s, _ = oracle.step(s, t, seed=13)
+        s, _ = oracle.step(s, t, seed=13, rules=rules)
     for t in reversed(range(n)):
-        s = inverse_step(s, t, 13)
+        s = inverse_step(s, t, 13, rules)
     np.testing.assert_array_equal(s, s0)
 
 
