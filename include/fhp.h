@@ -76,6 +76,16 @@ enum {
 enum { FHP_WALLS_NONE = 0, FHP_WALLS_CHANNEL = 1 };
 enum { FHP_CHIR_HASH = 0, FHP_CHIR_ZERO = 1, FHP_CHIR_ONE = 2 };
 
+/* Collision rule sets.  FHP_RULES_FHP2 is the model above.  FHP_RULES_FHP1:
+ * head-on pairs turn by +-60 degrees by the chirality bit and the symmetric
+ * triples swap, whatever the rest bit, which never changes.  FHP_RULES_FHP3
+ * (collision-saturated): FHP-II on states of at most three particles, plus the
+ * cycle A_j -> B_j -> C_j -> A_j (chirality 1; reversed for 0) with
+ * A_j = {j, j+1, j+4}, B_j = {j, j+2, j+5}, C_j = {j+1, j+5} + rest, and on
+ * states of four or more particles T(s) = ~T(~s) (particle-hole duality):
+ * every state that shares mass and momentum with another one changes. */
+enum { FHP_RULES_FHP2 = 0, FHP_RULES_FHP1 = 1, FHP_RULES_FHP3 = 2 };
+
 /* Observable kinds for fhp_observe. */
 enum {
     /* int64[11]: mass, p_x, p_y (momentum in units (1/2, sqrt(3)/2)),
@@ -96,7 +106,7 @@ typedef struct fhp_params {
     uint32_t height;      /* H: even, >= 2, < 2^20; W*H < 2^35 */
     uint32_t walls;       /* FHP_WALLS_* */
     uint32_t chirality;   /* FHP_CHIR_*; ZERO and ONE are test modes */
-    uint32_t reserved;    /* must be 0 */
+    uint32_t rules;       /* FHP_RULES_*; 0 = FHP-II (batches and pools take FHP-II only) */
     uint64_t seed;
     double fill;          /* per-channel occupancy of fluid nodes at t = 0, in [0, 1] */
     double force_rate;    /* forcing coin rate f per node and step, in [0, 1/64) */
@@ -122,7 +132,8 @@ int fhp_create(const fhp_params *p, void *dev_ws, size_t ws_bytes, void *hip_str
 
 /* Temporal-block depth k (1..FHP_MAX_DEPTH): fhp_step runs k steps per pass over
  * HBM (the last pass of a call may be shorter).  0 selects the library's default
- * for this lattice.  k > 1 needs width <= 32768.  Results do not depend on k. */
+ * for this lattice.  k > 1 needs width <= 32768.  FHP_RULES_FHP3 lattices run
+ * passes of at most 2 steps whatever k.  Results do not depend on k. */
 int fhp_set_depth(fhp_sim *s, uint32_t k);
 int fhp_get_depth(const fhp_sim *s, uint32_t *k);
 

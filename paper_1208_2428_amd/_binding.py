@@ -18,6 +18,7 @@ MAX_DEPTH = 4
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_BUSY = 0, -1, -2, -3, -4, -5
 WALLS_NONE, WALLS_CHANNEL = 0, 1
 CHIR_HASH, CHIR_ZERO, CHIR_ONE = 0, 1, 2
+RULES_FHP2, RULES_FHP1, RULES_FHP3 = 0, 1, 2
 OBS_GLOBAL, OBS_BLOCKS, OBS_DIGEST = 0, 1, 2
 
 _ERRNAMES = {E_INVAL: "FHP_E_INVAL", E_NOMEM: "FHP_E_NOMEM", E_DEVICE: "FHP_E_DEVICE",
@@ -37,7 +38,7 @@ class Params(ctypes.Structure):
         ("height", ctypes.c_uint32),
         ("walls", ctypes.c_uint32),
         ("chirality", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("rules", ctypes.c_uint32),
         ("seed", ctypes.c_uint64),
         ("fill", ctypes.c_double),
         ("force_rate", ctypes.c_double),
@@ -136,14 +137,14 @@ def check(rc: int) -> None:
 
 
 def make_params(width, height, seed=0, fill=0.0, force_rate=0.0, walls=False,
-                chirality=CHIR_HASH, solid=None):
+                chirality=CHIR_HASH, solid=None, rules=RULES_FHP2):
     """Returns (Params, keepalive) where keepalive holds the mask buffer."""
     p = Params()
     p.abi_version = ABI_VERSION
     p.width, p.height = int(width), int(height)
     p.walls = WALLS_CHANNEL if walls else WALLS_NONE
     p.chirality = int(chirality)
-    p.reserved = 0
+    p.rules = int(rules)
     p.seed = int(seed) & (2**64 - 1)
     p.fill = float(fill)
     p.force_rate = float(force_rate)

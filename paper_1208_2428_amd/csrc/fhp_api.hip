@@ -75,7 +75,7 @@ int validate(const fhp_params* p) {
                     (unsigned long long)p->width * p->height);
     if (p->walls > FHP_WALLS_CHANNEL) return fail(FHP_E_INVAL, "walls %u unknown", p->walls);
     if (p->chirality > FHP_CHIR_ONE) return fail(FHP_E_INVAL, "chirality %u unknown", p->chirality);
-    if (p->reserved) return fail(FHP_E_INVAL, "reserved field must be 0");
+    if (p->rules > FHP_RULES_FHP3) return fail(FHP_E_INVAL, "rule set %u unknown", p->rules);
     if (!(p->fill >= 0.0 && p->fill <= 1.0)) return fail(FHP_E_INVAL, "fill must lie in [0, 1]");
     if (!(p->force_rate >= 0.0 && p->force_rate < 1.0 / 64.0))
         return fail(FHP_E_INVAL, "force_rate must lie in [0, 1/64)");
@@ -132,6 +132,7 @@ int sim_setup(fhp_sim* s, const fhp_params* p, uint64_t* planes, const Layout& l
     s->D.key_force = hash64(p->seed, kTagForce);
     s->D.thr_force = (uint64_t)floor(p->force_rate * 274877906944.0);  // f * 2^38
     s->D.chir_mode = p->chirality;
+    s->D.rules = p->rules;
     s->depth = default_depth(s->L.wd);
     s->band = 0;
 
@@ -217,9 +218,11 @@ int fhp_step(fhp_sim* s, uint64_t n) {
                     (unsigned long long)s->t, (unsigned long long)n);
     if (s->changed && n) *s->changed = 1;
     const Lattice L = lattice_of(s);
-    const uint32_t T = s->band ? s->band : default_band(s->L.H, s->depth);
+    uint32_t depth = s->depth;
+    if (s->D.rules == FHP_RULES_FHP3 && depth > kMaxDepthFHP3) depth = kMaxDepthFHP3;
+    const uint32_t T = s->band ? s->band : default_band(s->L.H, depth);
     while (n > 0) {
-        uint32_t k = (n >= s->depth) ? s->depth : (uint32_t)n;
+        uint32_t k = (n >= depth) ? depth : (uint32_t)n;
         if (k == 1)
             FHP_HIP_TRY(launch_step1(s->buf[s->cur], s->buf[1 - s->cur], L, s->D, s->t, s->st),
                         "step");

@@ -750,6 +750,9 @@ int batch_layout(const fhp_params* ps, uint32_t n, BatchLayout* bl) {
         if (ps[i].height < 2 * FHP_MAX_DEPTH)
             return fail(FHP_E_INVAL, "member %u: height %u below %u", i, ps[i].height,
                         2 * FHP_MAX_DEPTH);
+        if (ps[i].rules != FHP_RULES_FHP2)
+            return fail(FHP_E_INVAL, "member %u: rule set %u; batches run FHP-II only", i,
+                        ps[i].rules);
         bl->member_off[i] = off;
         off += round_up(layout_for(ps[i].width, ps[i].height).aux_off, 32);  // planes and S
         segs += ps[i].height / 2;  // bands of at least 2 rows
@@ -779,6 +782,8 @@ int pool_check(const fhp_params* p) {
         return fail(FHP_E_INVAL, "width %u above %u", p->width, 64 * kMaxBlockedWords);
     if (p->height < 2 * FHP_MAX_DEPTH)
         return fail(FHP_E_INVAL, "height %u below %u", p->height, 2 * FHP_MAX_DEPTH);
+    if (p->rules != FHP_RULES_FHP2)
+        return fail(FHP_E_INVAL, "rule set %u: batches and pools run FHP-II only", p->rules);
     return FHP_OK;
 }
 

@@ -63,47 +63,72 @@ FHP_HD uint32_t maj3(uint32_t a, uint32_t b, uint32_t c) {
 FHP_HD uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) { return lop3<kA ^ kB ^ kC>(a, b, c); }
 FHP_HD uint32_t or3(uint32_t a, uint32_t b, uint32_t c) { return lop3<kA | kB | kC>(a, b, c); }
 
-// Update of 32 nodes after streaming (FHP-II collision on fluid nodes,
-// bounce-back on solid nodes, then forcing).  a[0..5] moving channels, a[6]
-// rest, s solid, chi chirality, coin forcing coin (at most one bit).
+// Rule sets (the values of fhp_params.rules).
+constexpr int kRulesFHP2 = 0, kRulesFHP1 = 1, kRulesFHP3 = 2;
+
+// Particle counts of the six moving channels of 32 nodes, by parity class:
+// n = n0 + 2 n1 + 4 n2; se = parity of the even-class count; pp = a head-on
+// pair is present; eq024 = channels 0, 2, 4 all equal.
+struct Counts {
+    uint32_t se, n0, n1, n2, pp, eq024;
+};
+
+FHP_HD Counts counts(const uint32_t a[7]) {
+    Counts K;
+    K.se = xor3(a[0], a[2], a[4]);
+    const uint32_t ce = maj3(a[0], a[2], a[4]);
+    const uint32_t so = xor3(a[1], a[3], a[5]), co = maj3(a[1], a[3], a[5]);
+    K.n0 = K.se ^ so;
+    const uint32_t c0 = K.se & so;
+    K.n1 = xor3(ce, co, c0);
+    K.n2 = maj3(ce, co, c0);
+    uint32_t pp = a[0] & a[3];
+    pp = lop3<kA | (kB & kC)>(pp, a[1], a[4]);
+    K.pp = lop3<kA | (kB & kC)>(pp, a[2], a[5]);
+    K.eq024 = lop3<(kA & kB & kC) | (~kA & ~kB & ~kC)>(a[0], a[2], a[4]);
+    return K;
+}
+
+// Collision of 32 nodes after streaming (fluid nodes) and bounce-back (solid
+// nodes), FHP-II or FHP-I.  a[0..5] moving channels, a[6] rest, s solid, chi
+// chirality.
 //
 // Every colliding state maps each output channel j to a function of the two
 // channels next to it, A = a_{j-1} and B = a_{j+1} (indices mod 6):
 //   R1 head-on pair alone (rest particle a spectator): the pair turns by
 //      +60 deg (chi = 1) or -60 deg (chi = 0): o_j = chi ? A : B;
-//   R2 {0,2,4} <-> {1,3,5} without rest particle: o_j = A (= B);
-//   R3 one particle c plus rest -> {c-1, c+1}: o_j = A | B, and {c-1, c+1}
-//      without rest -> c plus rest: o_j = A & B; i.e. o_j = maj(rest, A, B),
-//      and the rest bit flips.
+//   R2 {0,2,4} <-> {1,3,5} (FHP-II: without rest particle): o_j = A (= B);
+//   R3 (FHP-II only) one particle c plus rest -> {c-1, c+1}: o_j = A | B,
+//      and {c-1, c+1} without rest -> c plus rest: o_j = A & B; i.e.
+//      o_j = maj(rest, A, B), and the rest bit flips.
 // Both forms are "A where A = B, else Z": Z = (chi XNOR A) for R1/R2 and
-// Z = rest for R3.  The rule that applies comes from the number n of moving
-// particles, counted by parity class (even channels 0, 2, 4 and odd 1, 3, 5
-// with full adders): R1 = (n = 2) & (an opposite pair present);
-// R3 = rest ? (n = 1) : ((n = 2) & both particles in one class, i.e. at
-// 120 deg); R2 = (n = 3) without rest, channels 0, 2, 4 equal.
-FHP_HD void update32(const uint32_t a[7], uint32_t s, uint32_t chi, uint32_t coin, uint32_t o[7]) {
+// Z = rest for R3.  The rule that applies comes from the number of moving
+// particles: R1 = (n = 2) & (an opposite pair present); R3 = rest ? (n = 1) :
+// ((n = 2) & both particles in one class, i.e. at 120 deg); R2 = (n = 3),
+// channels 0, 2, 4 equal (and no rest for FHP-II).
+template <int RULES>
+FHP_HD void collide_fhp12(const uint32_t a[7], const Counts& K, uint32_t s, uint32_t chi,
+                          uint32_t o[7]) {
     const uint32_t r = a[6];
-    // n = n0 + 2 n1 + 4 n2; se = parity of the even-class count
-    const uint32_t se = xor3(a[0], a[2], a[4]), ce = maj3(a[0], a[2], a[4]);
-    const uint32_t so = xor3(a[1], a[3], a[5]), co = maj3(a[1], a[3], a[5]);
-    const uint32_t n0 = se ^ so, c0 = se & so;
-    const uint32_t n1 = xor3(ce, co, c0), n2 = maj3(ce, co, c0);
-    const uint32_t is1 = lop3<kA & ~kB & ~kC>(n0, n1, n2);
-    const uint32_t is2 = lop3<~kA & kB & ~kC>(n0, n1, n2);
-    const uint32_t is3 = n0 & n1;  // n = 7 cannot occur
-    // an opposite (head-on) pair is present
-    uint32_t pp = a[0] & a[3];
-    pp = lop3<kA | (kB & kC)>(pp, a[1], a[4]);
-    pp = lop3<kA | (kB & kC)>(pp, a[2], a[5]);
-    const uint32_t eq024 = lop3<(kA & kB & kC) | (~kA & ~kB & ~kC)>(a[0], a[2], a[4]);
-    const uint32_t tri = lop3<kA & kB & ~kC>(is3, eq024, r);            // R2
-    const uint32_t c12 = lop3<((kA & kB) | kC) & 0xFF>(is2, pp, tri) & ~s;  // R1 or R2, fluid
-    const uint32_t f3 = lop3<kA & ~kB & ~kC>(is2, se, s);               // two at 120 deg, fluid
-    const uint32_t e3 = lop3<kA & kB & ~kC>(r, is1, s);                 // one + rest, fluid
-    const uint32_t c3 = lop3<(kA & kB) | (~kA & kC)>(r, e3, f3);        // R3, fluid
-    const uint32_t zc = lop3<(kA & ~kB) | (~kA & kC)>(c12, chi, r);     // c12 ? ~chi : r
-    const uint32_t any = c12 | c3;                                      // a rule applies
-    const uint32_t keep = lop3<~(kA | kB)>(any, s, 0);                  // unchanged node
+    const uint32_t is1 = lop3<kA & ~kB & ~kC>(K.n0, K.n1, K.n2);
+    const uint32_t is2 = lop3<~kA & kB & ~kC>(K.n0, K.n1, K.n2);
+    const uint32_t is3 = K.n0 & K.n1;  // n = 7 cannot occur
+    uint32_t c12, c3, zc;
+    if constexpr (RULES == kRulesFHP1) {
+        const uint32_t tri = is3 & K.eq024;                                   // R2
+        c12 = lop3<((kA & kB) | kC) & 0xFF>(is2, K.pp, tri) & ~s;             // R1 or R2, fluid
+        c3 = 0;
+        zc = ~chi;
+    } else {
+        const uint32_t tri = lop3<kA & kB & ~kC>(is3, K.eq024, r);          // R2
+        c12 = lop3<((kA & kB) | kC) & 0xFF>(is2, K.pp, tri) & ~s;             // R1 or R2, fluid
+        const uint32_t f3 = lop3<kA & ~kB & ~kC>(is2, K.se, s);             // two at 120 deg, fluid
+        const uint32_t e3 = lop3<kA & kB & ~kC>(r, is1, s);                 // one + rest, fluid
+        c3 = lop3<(kA & kB) | (~kA & kC)>(r, e3, f3);                       // R3, fluid
+        zc = lop3<(kA & ~kB) | (~kA & kC)>(c12, chi, r);                    // c12 ? ~chi : r
+    }
+    const uint32_t any = c12 | c3;                                          // a rule applies
+    const uint32_t keep = lop3<~(kA | kB)>(any, s, 0);                      // unchanged node
 #pragma unroll
     for (int j = 0; j < 6; j++) {
         const uint32_t am = a[(j + 5) % 6], ap = a[(j + 1) % 6];
@@ -113,7 +138,64 @@ FHP_HD void update32(const uint32_t a[7], uint32_t s, uint32_t chi, uint32_t coi
         o[j] = mux3(keep, a[j], alt);
     }
     o[6] = r ^ c3;
-    // forcing: bits 5 -> 2 where the coin is up, on fluid nodes with o5 set, o2 clear
+}
+
+// Collision-saturated FHP-III.  Nodes of mass >= 4 are handled through their
+// complement (particle-hole duality: T(s) = ~T(~s)), so the rules below act
+// on mass <= 3 only: FHP-II, plus for every spectator position j the cycle
+// A_j -> B_j -> C_j -> A_j (chi = 1; reversed for chi = 0) with
+//   A_j = {j, j+1, j+4}, B_j = {j, j+2, j+5}, C_j = {j+1, j+5} + rest.
+// Bounce-back commutes with the complement, so solid nodes need no care.
+FHP_HD void collide_fhp3(const uint32_t a[7], uint32_t s, uint32_t chi, uint32_t o[7]) {
+    const Counts K0 = counts(a);
+    // mass = n + rest >= 4  <=>  n >= 4, or n = 3 with a rest particle
+    const uint32_t cm = lop3<(kA & kB & kC)>(K0.n0, K0.n1, a[6]) | K0.n2;
+    uint32_t b[7];
+#pragma unroll
+    for (int c = 0; c < 7; c++) b[c] = a[c] ^ cm;
+    const Counts K = counts(b);
+    uint32_t ob[7];
+    collide_fhp12<kRulesFHP2>(b, K, s, chi, ob);
+    const uint32_t rb = b[6];
+    const uint32_t is3 = K.n0 & K.n1;
+    const uint32_t is2 = lop3<~kA & kB & ~kC>(K.n0, K.n1, K.n2);
+    // three moving with a head-on pair, no rest; two at 120 deg plus rest
+    const uint32_t p3 = lop3<kA & ~kB & ~kC>(is3 & K.pp, rb, s);
+    const uint32_t p2 = lop3<kA & ~kB & kC>(is2, K.se, rb) & ~s;
+    uint32_t tA[6], tB[6], tC[6];
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        const uint32_t iA = lop3<kA & kB & kC>(p3, b[j], b[(j + 1) % 6]) & b[(j + 4) % 6];
+        const uint32_t iB = lop3<kA & kB & kC>(p3, b[j], b[(j + 2) % 6]) & b[(j + 5) % 6];
+        const uint32_t iC = lop3<kA & kB & kC>(p2, b[(j + 1) % 6], b[(j + 5) % 6]);
+        tA[j] = mux3(chi, iC, iB);  // nodes whose result is A_j
+        tB[j] = mux3(chi, iA, iC);
+        tC[j] = mux3(chi, iB, iA);
+    }
+    const uint32_t cyc = p3 | p2;
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        // channel k is in A_j for j = k, k-1, k-4; in B_j for j = k, k-2, k-5;
+        // in C_j for j = k-1, k-5
+        const uint32_t x = or3(tA[k], tA[(k + 5) % 6], tA[(k + 2) % 6]);
+        const uint32_t y = or3(tB[k], tB[(k + 4) % 6], tB[(k + 1) % 6]);
+        const uint32_t w = or3(x, y, tC[(k + 5) % 6] | tC[(k + 1) % 6]);
+        o[k] = lop3<(kA & ~kB) | kC>(ob[k], cyc, w) ^ cm;
+    }
+    const uint32_t w6 = or3(or3(tC[0], tC[1], tC[2]), or3(tC[3], tC[4], tC[5]), 0);
+    o[6] = lop3<(kA & ~kB) | kC>(ob[6], cyc, w6) ^ cm;
+}
+
+// Update of 32 nodes after streaming: collision (fluid) or bounce-back
+// (solid) of rule set RULES, then forcing: bits 5 -> 2 where the coin is up,
+// on fluid nodes with o5 set and o2 clear.  coin has at most one bit.
+template <int RULES = kRulesFHP2>
+FHP_HD void update32(const uint32_t a[7], uint32_t s, uint32_t chi, uint32_t coin, uint32_t o[7]) {
+    if constexpr (RULES == kRulesFHP3) {
+        collide_fhp3(a, s, chi, o);
+    } else {
+        collide_fhp12<RULES>(a, counts(a), s, chi, o);
+    }
     const uint32_t cf = coin & ~s;
     const uint32_t o5 = lop3<kA & ~(kB & ~kC)>(o[5], cf, o[2]);
     const uint32_t o2 = lop3<kA | (kB & kC)>(o[2], cf, o[5]);
@@ -122,6 +204,7 @@ FHP_HD void update32(const uint32_t a[7], uint32_t s, uint32_t chi, uint32_t coi
 }
 
 // 64-node version: the two 32-bit halves independently.
+template <int RULES = kRulesFHP2>
 FHP_HD void update(const uint64_t a[7], uint64_t solid, uint64_t chi, uint64_t coin,
                    uint64_t o[7]) {
     uint32_t lo[7], hi[7], olo[7], ohi[7];
@@ -129,8 +212,8 @@ FHP_HD void update(const uint64_t a[7], uint64_t solid, uint64_t chi, uint64_t c
         lo[c] = (uint32_t)a[c];
         hi[c] = (uint32_t)(a[c] >> 32);
     }
-    update32(lo, (uint32_t)solid, (uint32_t)chi, (uint32_t)coin, olo);
-    update32(hi, (uint32_t)(solid >> 32), (uint32_t)(chi >> 32), (uint32_t)(coin >> 32), ohi);
+    update32<RULES>(lo, (uint32_t)solid, (uint32_t)chi, (uint32_t)coin, olo);
+    update32<RULES>(hi, (uint32_t)(solid >> 32), (uint32_t)(chi >> 32), (uint32_t)(coin >> 32), ohi);
     for (int c = 0; c < 7; c++) o[c] = ((uint64_t)ohi[c] << 32) | olo[c];
 }
 

@@ -23,7 +23,13 @@ struct Dyn {
     uint64_t key_chir = 0, key_force = 0;
     uint64_t thr_force = 0;  // floor(f * 2^38)
     uint32_t chir_mode = 0;  // FHP_CHIR_*
+    uint32_t rules = 0;      // FHP_RULES_*
 };
+
+// FHP-III's collision holds about three times the live values of FHP-II's;
+// with more than two levels in registers the blocked kernel would spill, so
+// passes of an FHP-III lattice are at most two steps deep.
+constexpr uint32_t kMaxDepthFHP3 = 2;
 
 // Workspace layout of one lattice: [buffer 0: 7 planes][buffer 1: 7 planes]
 // [S plane][aux].

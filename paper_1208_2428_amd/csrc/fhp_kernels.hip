@@ -195,6 +195,7 @@ __global__ void __launch_bounds__(kBlock) k_digest(const uint64_t* __restrict__ 
 //   c0 (SW): row y+1, rotr1 if y odd        c1 (SE): row y+1, rotl1 if y even
 // The carry bit of a shifted word comes from the neighbouring word of the
 // same row (periodic in x).  Then collision / bounce-back / forcing.
+template <int RULES>
 __global__ void __launch_bounds__(kBlock) k_step1(const uint64_t* __restrict__ in,
                                                   uint64_t* __restrict__ out, Lattice L, Dyn D,
                                                   uint64_t t) {
@@ -228,7 +229,7 @@ __global__ void __launch_bounds__(kBlock) k_step1(const uint64_t* __restrict__ i
     else chi = (D.chir_mode == FHP_CHIR_ONE) ? ~0ull : 0ull;
     const uint64_t coin = D.thr_force ? coin_word(hash64(D.key_force, ctr), D.thr_force) : 0ull;
     uint64_t o[7];
-    update(a, solid, chi, coin, o);
+    update<RULES>(a, solid, chi, coin, o);
 #pragma unroll
     for (int c = 0; c < 7; c++) out[c * ps + idx] = o[c];
 }
@@ -302,8 +303,13 @@ hipError_t launch_digest(const uint64_t* planes, const Lattice& L, uint64_t* acc
 
 hipError_t launch_step1(const uint64_t* in, uint64_t* out, const Lattice& L, const Dyn& D,
                         uint64_t t, hipStream_t st) {
-    hipLaunchKernelGGL(k_step1, dim3(grid_for((size_t)L.H * L.wd)), dim3(kBlock), 0, st, in, out,
-                       L, D, t);
+    const dim3 grid(grid_for((size_t)L.H * L.wd));
+    if (D.rules == kRulesFHP1)
+        hipLaunchKernelGGL(k_step1<kRulesFHP1>, grid, dim3(kBlock), 0, st, in, out, L, D, t);
+    else if (D.rules == kRulesFHP3)
+        hipLaunchKernelGGL(k_step1<kRulesFHP3>, grid, dim3(kBlock), 0, st, in, out, L, D, t);
+    else
+        hipLaunchKernelGGL(k_step1<kRulesFHP2>, grid, dim3(kBlock), 0, st, in, out, L, D, t);
     return hipGetLastError();
 }
 

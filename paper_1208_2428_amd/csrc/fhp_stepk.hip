@@ -46,7 +46,7 @@ struct StepkArgs {
     uint64_t chi_and, chi_or;  // chirality word = (hash & chi_and) | chi_or
 };
 
-template <int K, bool FORCE, bool MASK>
+template <int K, bool FORCE, bool MASK, int RULES>
 __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
                                                 uint64_t* __restrict__ out,
                                                 const uint64_t* __restrict__ S, StepkArgs a) {
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
             const uint64_t chi = (mix64(base_chi + R) & a.chi_and) | a.chi_or;
             const uint64_t coin = FORCE ? coin_word(mix64(base_frc + R), a.thr_force) : 0ull;
             Row Y;
-            update(n, sw, chi, coin, Y.p);
+            update<RULES>(n, sw, chi, coin, Y.p);
             Y.s = sw;
             push(lc, X);
             if (l < K) {
@@ -167,20 +167,31 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
     }
 }
 
-template <int K, bool FORCE, bool MASK>
+template <int K, bool FORCE, bool MASK, int RULES = kRulesFHP2>
 hipError_t launch_k(const uint64_t* in, uint64_t* out, const Lattice& L, const StepkArgs& a,
                     hipStream_t st) {
     const uint32_t nt = (L.wd + 63) / 64 * 64;
     const uint32_t bands = (L.H + a.T - 1) / a.T;
-    hipLaunchKernelGGL((k_stepk<K, FORCE, MASK>), dim3(bands), dim3(nt), 2 * nt * sizeof(uint32_t),
-                       st, in, out, L.S, a);
+    hipLaunchKernelGGL((k_stepk<K, FORCE, MASK, RULES>), dim3(bands), dim3(nt),
+                       2 * nt * sizeof(uint32_t), st, in, out, L.S, a);
     return hipGetLastError();
 }
 
+// FHP-II has a kernel for every combination of forcing and obstacles; the
+// other rule sets use the forcing variant (a zero rate draws no coin).
 template <int K>
 hipError_t launch_k2(const uint64_t* in, uint64_t* out, const Lattice& L, const StepkArgs& a,
-                     hipStream_t st) {
+                     uint32_t rules, hipStream_t st) {
     const bool force = a.thr_force != 0, mask = L.S != nullptr;
+    if (rules == kRulesFHP1)
+        return mask ? launch_k<K, true, true, kRulesFHP1>(in, out, L, a, st)
+                    : launch_k<K, true, false, kRulesFHP1>(in, out, L, a, st);
+    if (rules == kRulesFHP3) {
+        if constexpr (K <= kMaxDepthFHP3)
+            return mask ? launch_k<K, true, true, kRulesFHP3>(in, out, L, a, st)
+                        : launch_k<K, true, false, kRulesFHP3>(in, out, L, a, st);
+        return hipErrorInvalidValue;
+    }
     if (force) return mask ? launch_k<K, true, true>(in, out, L, a, st)
                            : launch_k<K, true, false>(in, out, L, a, st);
     return mask ? launch_k<K, false, true>(in, out, L, a, st)
@@ -204,10 +215,10 @@ hipError_t launch_stepk(uint32_t K, const uint64_t* in, uint64_t* out, const Lat
     a.chi_and = (D.chir_mode == FHP_CHIR_HASH) ? ~0ull : 0ull;
     a.chi_or = (D.chir_mode == FHP_CHIR_ONE) ? ~0ull : 0ull;
     switch (K) {
-        case 1: return launch_k2<1>(in, out, L, a, st);
-        case 2: return launch_k2<2>(in, out, L, a, st);
-        case 3: return launch_k2<3>(in, out, L, a, st);
-        case 4: return launch_k2<4>(in, out, L, a, st);
+        case 1: return launch_k2<1>(in, out, L, a, D.rules, st);
+        case 2: return launch_k2<2>(in, out, L, a, D.rules, st);
+        case 3: return launch_k2<3>(in, out, L, a, D.rules, st);
+        case 4: return launch_k2<4>(in, out, L, a, D.rules, st);
         default: return hipErrorInvalidValue;
     }
 }

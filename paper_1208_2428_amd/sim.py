@@ -27,14 +27,15 @@ class Sim:
     def __init__(self, width: int, height: int, seed: int = 0, fill: float = 0.0,
                  force_rate: float = 0.0, walls: bool = False, chirality: int = B.CHIR_HASH,
                  solid: np.ndarray | None = None, device=None, stream=None, depth: int = 0,
-                 band: int = 0):
+                 band: int = 0, rules: int = B.RULES_FHP2):
         lib = B.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the FHP library needs a ROCm GPU (torch.cuda is unavailable)")
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)
         self.width, self.height = int(width), int(height)
-        params, keep = B.make_params(width, height, seed, fill, force_rate, walls, chirality, solid)
+        params, keep = B.make_params(width, height, seed, fill, force_rate, walls, chirality, solid,
+                                     rules)
         nbytes = B.workspace_bytes(params)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self._stream = stream

@@ -1,6 +1,6 @@
 // Host build of the GPU library's per-word update (fhp_device.h) checked
-// against the CPU oracle's collision table, for every 7-bit state, both
-// chiralities, fluid and solid nodes, and the forcing swap.  Test code only:
+// against the CPU oracle's collision tables of the three rule sets, for every
+// 7-bit state, both chiralities, fluid and solid nodes, and the forcing swap.  Test code only:
 // it links the oracle and includes the library header side by side.
 #include <stdio.h>
 
@@ -9,10 +9,14 @@ extern "C" {
 #include "../../oracle/fhp_oracle.h"
 }
 
-int main() {
+// Every (state, chirality) pair of rule set RULES, on fluid and solid nodes.
+template <int RULES>
+int check_rules(int oracle_rules) {
     uint8_t table[2][128];
-    fhpo_collision_table(0, table[0]);
-    fhpo_collision_table(1, table[1]);
+    if (fhpo_rule_table(oracle_rules, 0, table[0]) || fhpo_rule_table(oracle_rules, 1, table[1])) {
+        printf("rule set %d unknown to the oracle\n", oracle_rules);
+        return 1;
+    }
     int bad = 0;
     // 256 (state, chirality) combinations in four words of 64 nodes
     for (int k = 0; k < 4; k++) {
@@ -25,7 +29,7 @@ int main() {
         }
         for (int solid = 0; solid < 2; solid++) {
             uint64_t o[7];
-            fhp::update(a, solid ? ~0ull : 0ull, chi, 0, o);
+            fhp::update<RULES>(a, solid ? ~0ull : 0ull, chi, 0, o);
             for (int b = 0; b < 64; b++) {
                 const int combo = k * 64 + b, s = combo & 127;
                 int got = 0;
@@ -39,23 +43,31 @@ int main() {
                 }
                 if (got != want) {
                     if (bad < 10)
-                        printf("state %d chi %d solid %d: got %d want %d\n", s, combo >> 7, solid,
-                               got, want);
+                        printf("rules %d state %d chi %d solid %d: got %d want %d\n", oracle_rules,
+                               s, combo >> 7, solid, got, want);
                     bad++;
                 }
             }
         }
     }
-    // forcing: lone W-movers (no collision); coin on node 17 flips it to E on
-    // a fluid node, and does nothing on a solid node (which bounces it back)
+    // forcing: lone W-movers (no collision in any rule set); coin on node 17
+    // flips it to E on a fluid node, and does nothing on a solid node (which
+    // bounces it back)
     {
         uint64_t a[7] = {0}, o[7];
         a[5] = ~0ull;
-        fhp::update(a, 0, 0, 1ull << 17, o);
+        fhp::update<RULES>(a, 0, 0, 1ull << 17, o);
         if (o[5] != ~(1ull << 17) || o[2] != (1ull << 17)) bad++, printf("forcing on fluid\n");
-        fhp::update(a, 1ull << 17, 0, 1ull << 17, o);
+        fhp::update<RULES>(a, 1ull << 17, 0, 1ull << 17, o);
         if (o[2] != (1ull << 17) || o[5] != ~(1ull << 17)) bad++, printf("forcing on solid\n");
     }
+    return bad;
+}
+
+int main() {
+    int bad = check_rules<fhp::kRulesFHP2>(FHPO_RULES_FHP2);
+    bad += check_rules<fhp::kRulesFHP1>(FHPO_RULES_FHP1);
+    bad += check_rules<fhp::kRulesFHP3>(FHPO_RULES_FHP3);
     // the hash: SplitMix64 output 1 of state 1234567
     if (fhp::hash64(1234567, 0) != 6457827717110365317ull) bad++, printf("hash\n");
     // split hash = direct hash

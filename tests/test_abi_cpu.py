@@ -104,3 +104,17 @@ def test_batch_and_pool_argument_checks(lib):
                                ctypes.byref(h)) == B.E_NOMEM   # arena smaller than its tables
     assert lib.fhp_pool_tick(None, 1) == B.E_INVAL
     assert lib.fhp_batch_step(None, 1) == B.E_INVAL
+
+
+def test_rule_set_checks(lib):
+    n = ctypes.c_size_t()
+    for rules in (B.RULES_FHP2, B.RULES_FHP1, B.RULES_FHP3):
+        p, _ = B.make_params(128, 64, rules=rules)
+        assert lib.fhp_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == B.OK
+    p, _ = B.make_params(128, 64, rules=3)
+    assert lib.fhp_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == B.E_INVAL
+    # batches and pools run FHP-II only, and say so before touching the device
+    arr = (B.Params * 1)()
+    arr[0], _ = B.make_params(128, 64, rules=B.RULES_FHP3)
+    assert lib.fhp_batch_workspace_bytes(arr, 1, ctypes.byref(n)) == B.E_INVAL
+    assert b"FHP-II" in lib.fhp_last_error()
