@@ -47,8 +47,8 @@ def recorded_traffic(name: str, depth: int):
     sources or another depth."""
     from paper_1208_2428_amd import profsum
     path = os.path.join(ROOT, "profiles", f"k_stepk_{name}.md")
-    traffic, src = profsum.recorded_traffic(path)
-    if traffic is None or depth != 4 or src != profsum.kernel_source_hash():
+    traffic, src, rec_depth = profsum.recorded_traffic(path)
+    if traffic is None or depth != rec_depth or src != profsum.kernel_source_hash():
         return None
     return traffic
 
@@ -98,20 +98,64 @@ def batched_leg(args, wl, mask, depth, value):
     log(f"bench: ensemble of {len(params)} lattices, {args.ensemble_steps} steps (tuning first)")
     res = ensemble.run_batched(params, args.ensemble_steps, log=log)
     k = res["tiling"]["depth"]
-    plain = value if k == depth else plain_rate(wl, mask, k, 240)
+    plain = value if k == depth else plain_rate(wl, mask, k, 480)
     log(f"bench: ensemble {res['value']:.3e} node-updates/s at depth {k}; plain {plain:.3e}")
     one = ensemble.run_one_by_one(params, args.ensemble_steps)
     log(f"bench: ensemble one lattice at a time: {one['value']:.3e} node-updates/s")
     return {"value": res["value"], "unit": "node-updates/s", "lattices": res["lattices"],
             "nodes": res["nodes"], "steps": res["steps"], "tiling": res["tiling"],
             "plain_value_same_depth": plain, "ratio_vs_plain": res["value"] / plain,
+            "ratio_vs_headline": res["value"] / value,
             "one_by_one_value": one["value"], "ratio_vs_one_by_one": res["value"] / one["value"]}
 
 
-def served_leg(args, plain, depth):
-    """Continuous batching of a Poisson stream of channel-flow jobs."""
+def rules_leg(args, wl, mask, plain):
+    """The headline workload under the other rule sets (FHP-I, FHP-III), each
+    at its default depth: throughput and per-launch HBM roofline fraction."""
+    import torch
+
+    from paper_1208_2428_amd import Sim
+    from paper_1208_2428_amd import _binding as B
+    stream = torch.cuda.current_stream()
+    nodes = wl.width * wl.height
+    out = {}
+    for name, rules, max_depth in (("fhp1", B.RULES_FHP1, B.MAX_DEPTH), ("fhp3", B.RULES_FHP3, 3)):
+        sim = Sim(**wl.params(), solid=mask, rules=rules)
+        depth = min(sim.depth, max_depth)  # steps per launch
+        sim.step(8 * depth)
+        torch.cuda.synchronize()
+        steps = args.rules_steps
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        launches = 50
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(launches)]
+        for a, b in evs:
+            a.record(stream)
+            sim.step(depth)
+            b.record(stream)
+        torch.cuda.synchronize()
+        launch_s = sum(a.elapsed_time(b) for a, b in evs) / launches / 1e3
+        sim.close()
+        achieved = PLANE_BITS * nodes / 8 / launch_s / 1e9
+        value = nodes * steps / wall
+        out[name] = {"value": value, "unit": "node-updates/s", "depth": depth, "steps": steps,
+                     "ratio_vs_fhp2": value / plain, "kernel_us": launch_s * 1e6,
+                     "roofline_frac": achieved / HBM_PEAK_GBS}
+        log(f"bench: {name} {value:.3e} node-updates/s at depth {depth}")
+    return out
+
+
+def served_leg(args, wl, mask, value, depth):
+    """Continuous batching of a Poisson stream of channel-flow jobs, at the
+    deepest depth pools take; compared with the plain kernel at that depth."""
+    from paper_1208_2428_amd import _binding as B
     from paper_1208_2428_amd import serve
     from paper_1208_2428_amd import workloads as WL
+    depth = min(depth, B.BATCH_MAX_DEPTH)
+    plain = plain_rate(wl, mask, depth, 480)
     reqs = WL.request_stream(n=args.serve_requests, rate=200.0, seed=5)
     offered = serve.offered_load(reqs)
     log(f"bench: serving {len(reqs)} requests at 200/s (offered {offered:.3e} node-updates/s)")
@@ -128,7 +172,9 @@ def served_leg(args, plain, depth):
     srv.close()
     keys = ("requests", "completed", "seconds", "value", "p50_ms", "p99_ms", "mean_ms",
             "max_queue", "max_resident", "ticks")
-    return {"value": hot["value"], "unit": "node-updates/s", "ratio_vs_plain": hot["value"] / plain,
+    return {"value": hot["value"], "unit": "node-updates/s", "depth": depth,
+            "plain_value_same_depth": plain, "ratio_vs_plain": hot["value"] / plain,
+            "ratio_vs_headline": hot["value"] / value,
             "offered_load": offered, "rate_per_s": 200.0, "arena_bytes": 32 << 30,
             "overloaded": {k: hot[k] for k in keys},
             "at_80pct_capacity": dict({k: at80[k] for k in keys}, rate_per_s=rate80,
@@ -150,6 +196,9 @@ def main() -> int:
     ap.add_argument("--ensemble-steps", type=int, default=500)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--no-rules", action="store_true",
+                    help="skip the FHP-I / FHP-III rule-set leg")
+    ap.add_argument("--rules-steps", type=int, default=400)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -234,7 +283,9 @@ def main() -> int:
     if not args.no_ensemble:
         out["batched"] = batched_leg(args, wl, mask, depth, value)
     if not args.no_serve:
-        out["served"] = served_leg(args, value, depth)
+        out["served"] = served_leg(args, wl, mask, value, depth)
+    if not args.no_rules:
+        out["rule_sets"] = rules_leg(args, wl, mask, value)
     if not args.no_cpu_baseline:
         log(f"bench: timing the CPU oracle for ~{args.cpu_seconds:.0f} s")
         out["cpu_baseline"] = cpu_baseline(wl, mask, args.cpu_seconds)

@@ -62,7 +62,8 @@ extern "C" {
 #endif
 
 #define FHP_ABI_VERSION 1u
-#define FHP_MAX_DEPTH 4u /* largest temporal-block depth k of one HBM pass */
+#define FHP_MAX_DEPTH 5u       /* largest temporal-block depth k of one HBM pass */
+#define FHP_BATCH_MAX_DEPTH 4u /* the same for batches and pools */
 
 enum {
     FHP_OK = 0,
@@ -132,8 +133,9 @@ int fhp_create(const fhp_params *p, void *dev_ws, size_t ws_bytes, void *hip_str
 
 /* Temporal-block depth k (1..FHP_MAX_DEPTH): fhp_step runs k steps per pass over
  * HBM (the last pass of a call may be shorter).  0 selects the library's default
- * for this lattice.  k > 1 needs width <= 32768.  FHP_RULES_FHP3 lattices run
- * passes of at most 2 steps whatever k.  Results do not depend on k. */
+ * for this lattice (FHP_MAX_DEPTH).  k > 1 needs width <= 32768.
+ * FHP_RULES_FHP3 lattices run passes of at most 3 steps whatever k.  Results
+ * do not depend on k. */
 int fhp_set_depth(fhp_sim *s, uint32_t k);
 int fhp_get_depth(const fhp_sim *s, uint32_t *k);
 
@@ -178,7 +180,7 @@ void fhp_destroy(fhp_sim *s);
  * two neighbouring bands' previous pass (per-band counters on the device).
  * Each member's results are identical to those of a standalone simulation with
  * the same parameters (Sec. 2 model; the same readings as above).
- * Members need width <= 32768 and height >= 2*FHP_MAX_DEPTH.
+ * Members need width <= 32768 and height >= 2*FHP_BATCH_MAX_DEPTH.
  * ------------------------------------------------------------------------- */
 typedef struct fhp_batch fhp_batch;
 
@@ -192,7 +194,7 @@ int fhp_batch_workspace_bytes(const fhp_params *ps, uint32_t n, size_t *bytes);
 int fhp_batch_create(const fhp_params *ps, uint32_t n, void *dev_ws, size_t ws_bytes,
                      void *hip_stream, fhp_batch **out);
 
-/* Tiling of the batch kernel: depth K (0 = FHP_MAX_DEPTH), target band height
+/* Tiling of the batch kernel: depth K (0 = FHP_BATCH_MAX_DEPTH), target band height
  * (0 = 32; per member the largest even divisor of H not above it and >= K),
  * threads per workgroup (0 = smallest multiple of 64 holding the widest row),
  * passes per launch (1 = one launch per pass; 0 = all passes of an
@@ -243,7 +245,7 @@ int fhp_pool_workspace_bytes(uint32_t max_slots, uint32_t max_bands, size_t latt
 int fhp_pool_create(void *dev_arena, size_t arena_bytes, uint32_t max_slots, uint32_t max_bands,
                     void *hip_stream, fhp_pool **out);
 
-/* Depth (0 = FHP_MAX_DEPTH), target band height (0 = 32) and workgroup size
+/* Depth (0 = FHP_BATCH_MAX_DEPTH), target band height (0 = 32) and workgroup size
  * (0 = smallest that holds the widest row) of the pool's launches; only while
  * the pool is empty. */
 int fhp_pool_set_tiling(fhp_pool *pl, uint32_t depth, uint32_t band, uint32_t group_threads);

@@ -402,7 +402,7 @@ struct Engine {
     uint32_t* done = nullptr;
     uint32_t max_members = 0, max_segs = 0;
     // tiling
-    uint32_t depth = FHP_MAX_DEPTH, band = 32, nt_req = 0, passes_per_launch = 1;
+    uint32_t depth = FHP_BATCH_MAX_DEPTH, band = 32, nt_req = 0, passes_per_launch = 1;
     int use_graph = 1;
     // current tables
     uint32_t nt = 64, n_groups = 0, n_done = 0, n_members = 0;
@@ -747,9 +747,9 @@ int batch_layout(const fhp_params* ps, uint32_t n, BatchLayout* bl) {
         if (ps[i].width / 64 > kMaxBlockedWords)
             return fail(FHP_E_INVAL, "member %u: width %u above %u", i, ps[i].width,
                         64 * kMaxBlockedWords);
-        if (ps[i].height < 2 * FHP_MAX_DEPTH)
+        if (ps[i].height < 2 * FHP_BATCH_MAX_DEPTH)
             return fail(FHP_E_INVAL, "member %u: height %u below %u", i, ps[i].height,
-                        2 * FHP_MAX_DEPTH);
+                        2 * FHP_BATCH_MAX_DEPTH);
         if (ps[i].rules != FHP_RULES_FHP2)
             return fail(FHP_E_INVAL, "member %u: rule set %u; batches run FHP-II only", i,
                         ps[i].rules);
@@ -780,8 +780,8 @@ int pool_check(const fhp_params* p) {
     if (rc) return rc;
     if (p->width / 64 > kMaxBlockedWords)
         return fail(FHP_E_INVAL, "width %u above %u", p->width, 64 * kMaxBlockedWords);
-    if (p->height < 2 * FHP_MAX_DEPTH)
-        return fail(FHP_E_INVAL, "height %u below %u", p->height, 2 * FHP_MAX_DEPTH);
+    if (p->height < 2 * FHP_BATCH_MAX_DEPTH)
+        return fail(FHP_E_INVAL, "height %u below %u", p->height, 2 * FHP_BATCH_MAX_DEPTH);
     if (p->rules != FHP_RULES_FHP2)
         return fail(FHP_E_INVAL, "rule set %u: batches and pools run FHP-II only", p->rules);
     return FHP_OK;
@@ -846,10 +846,10 @@ int fhp_batch_create(const fhp_params* ps, uint32_t n, void* dev_ws, size_t ws_b
 int fhp_batch_set_tiling(fhp_batch* b, uint32_t depth, uint32_t band, uint32_t group_threads,
                          uint32_t passes_per_launch) {
     if (!b) return fail(FHP_E_INVAL, "batch is NULL");
-    if (depth > FHP_MAX_DEPTH) return fail(FHP_E_INVAL, "depth %u above %u", depth, FHP_MAX_DEPTH);
+    if (depth > FHP_BATCH_MAX_DEPTH) return fail(FHP_E_INVAL, "depth %u above %u", depth, FHP_BATCH_MAX_DEPTH);
     if (group_threads % 64 || group_threads > 512)
         return fail(FHP_E_INVAL, "group_threads %u: a multiple of 64 up to 512", group_threads);
-    b->eng.depth = depth ? depth : FHP_MAX_DEPTH;
+    b->eng.depth = depth ? depth : FHP_BATCH_MAX_DEPTH;
     b->eng.band = band ? band : 32;
     b->eng.nt_req = group_threads;
     b->eng.passes_per_launch = passes_per_launch;
@@ -944,12 +944,12 @@ int fhp_pool_create(void* dev_arena, size_t arena_bytes, uint32_t max_slots, uin
 
 int fhp_pool_set_tiling(fhp_pool* pl, uint32_t depth, uint32_t band, uint32_t group_threads) {
     if (!pl) return fail(FHP_E_INVAL, "pool is NULL");
-    if (depth > FHP_MAX_DEPTH) return fail(FHP_E_INVAL, "depth %u above %u", depth, FHP_MAX_DEPTH);
+    if (depth > FHP_BATCH_MAX_DEPTH) return fail(FHP_E_INVAL, "depth %u above %u", depth, FHP_BATCH_MAX_DEPTH);
     if (group_threads % 64 || group_threads > 512)
         return fail(FHP_E_INVAL, "group_threads %u: a multiple of 64 up to 512", group_threads);
     for (auto& s : pl->slots)
         if (s.used) return fail(FHP_E_STATE, "tiling can change only while the pool is empty");
-    pl->eng.depth = depth ? depth : FHP_MAX_DEPTH;
+    pl->eng.depth = depth ? depth : FHP_BATCH_MAX_DEPTH;
     pl->eng.band = band ? band : 32;
     pl->eng.nt_req = group_threads;
     return FHP_OK;

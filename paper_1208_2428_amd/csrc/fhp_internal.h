@@ -26,10 +26,10 @@ struct Dyn {
     uint32_t rules = 0;      // FHP_RULES_*
 };
 
-// FHP-III's collision holds about three times the live values of FHP-II's;
-// with more than two levels in registers the blocked kernel would spill, so
-// passes of an FHP-III lattice are at most two steps deep.
-constexpr uint32_t kMaxDepthFHP3 = 2;
+// FHP-III's collision holds many more live values than FHP-II's; with more
+// than three levels in registers the blocked kernel would spill, so passes
+// of an FHP-III lattice are at most three steps deep.
+constexpr uint32_t kMaxDepthFHP3 = 3;
 
 // Workspace layout of one lattice: [buffer 0: 7 planes][buffer 1: 7 planes]
 // [S plane][aux].

@@ -219,6 +219,7 @@ hipError_t launch_stepk(uint32_t K, const uint64_t* in, uint64_t* out, const Lat
         case 2: return launch_k2<2>(in, out, L, a, D.rules, st);
         case 3: return launch_k2<3>(in, out, L, a, D.rules, st);
         case 4: return launch_k2<4>(in, out, L, a, D.rules, st);
+        case 5: return launch_k2<5>(in, out, L, a, D.rules, st);
         default: return hipErrorInvalidValue;
     }
 }

@@ -55,15 +55,17 @@ def pmc_summary(path: str, match: str | None = None) -> dict:
     return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}
 
 
-def recorded_traffic(profile_md: str) -> tuple[float | None, str | None]:
-    """(bytes per launch, kernel source hash) recorded in a profiles/ note."""
+def recorded_traffic(profile_md: str) -> tuple[float | None, str | None, int | None]:
+    """(bytes per launch, kernel source hash, depth) recorded in a profiles/ note."""
     try:
         text = open(profile_md).read()
     except OSError:
-        return None, None
+        return None, None, None
     m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
     s = re.search(r"kernel_source_hash:\s*([0-9a-f]+)", text)
-    return (float(m.group(1)) if m else None), (s.group(1) if s else None)
+    d = re.search(r"traffic_depth:\s*([0-9]+)", text)
+    return ((float(m.group(1)) if m else None), (s.group(1) if s else None),
+            (int(d.group(1)) if d else None))
 
 
 def main(argv):

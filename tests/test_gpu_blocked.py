@@ -30,7 +30,7 @@ def make_state(rng, W, H, case):
 
 
 @pytest.mark.parametrize("W,H", [(64, 2), (64, 6), (192, 10), (320, 34), (1024, 70), (4096, 40)])
-@pytest.mark.parametrize("K", [2, 3, 4])
+@pytest.mark.parametrize("K", [2, 3, 4, 5])
 @pytest.mark.parametrize("case", ["walls+force", "mask+force", "solid-particles"])
 def test_depths_every_pass(W, H, K, case):
     say("blocked", W, H, K, case)
@@ -64,7 +64,7 @@ def test_band_heights(band, K):
     np.testing.assert_array_equal(s.get_state(), ref)
 
 
-@pytest.mark.parametrize("K", [1, 2, 3, 4])
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 5])
 def test_depth_does_not_change_workload_result(K):
     # The channel workload at reduced size, 48 steps: every depth gives the
     # oracle's state.
@@ -79,7 +79,7 @@ def test_depth_does_not_change_workload_result(K):
 
 def test_fixed_points_blocked():
     for v in (0x00, 0x7F):
-        s = Sim(256, 20, seed=4, depth=4)
+        s = Sim(256, 20, seed=4, depth=5)
         s.set_state(np.full((20, 256), v, np.uint8), 0)
         s.step(9)
         assert np.all(s.get_state() == v)

@@ -31,7 +31,7 @@ def records(name):
 
 
 @pytest.mark.parametrize("name", ["channel-4096", "porous-16384"])
-@pytest.mark.parametrize("depth", [1, 3, 4])
+@pytest.mark.parametrize("depth", [1, 3, 4, 5])
 def test_workload_matches_oracle_digests(name, depth):
     recs = records(name)
     wl = WL.WORKLOADS[name]

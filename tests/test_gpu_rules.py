@@ -35,7 +35,7 @@ def make_state(rng, W, H, case):
 
 @pytest.mark.parametrize("name", list(RULES))
 @pytest.mark.parametrize("W,H", [(64, 2), (192, 10), (320, 34), (1024, 70)])
-@pytest.mark.parametrize("K", [1, 2, 3, 4])
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("case", ["torus", "walls+force", "mask+force", "solid-particles"])
 def test_rules_match_oracle(name, W, H, K, case):
     say("rules", name, W, H, K, case)
