@@ -98,7 +98,10 @@ enum {
     FHP_OBS_BLOCKS = 1,
     /* uint64[1]: sum over planes c = 0..7 (7 = solid), rows y and words w of
      * H(word, c*2^40 + y*2^20 + w) mod 2^64. */
-    FHP_OBS_DIGEST = 2
+    FHP_OBS_DIGEST = 2,
+    /* int64[H][3]: (rho, p_x, p_y) summed over each row, e.g. for the velocity
+     * profile across a channel (the flows of Sec. 2 and Sec. 4). */
+    FHP_OBS_ROWS = 3
 };
 
 typedef struct fhp_params {

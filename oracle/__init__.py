@@ -76,6 +76,8 @@ def _load():
                                    ctypes.c_int, ctypes.c_int, i64p]
     lib.fhpo_observe_global.restype = None
     lib.fhpo_observe_global.argtypes = [u8p, ctypes.c_uint32, ctypes.c_uint32, i64p]
+    lib.fhpo_observe_rows.restype = None
+    lib.fhpo_observe_rows.argtypes = [u8p, ctypes.c_uint32, ctypes.c_uint32, i64p]
     lib.fhpo_observe_blocks.restype = ctypes.c_int
     lib.fhpo_observe_blocks.argtypes = [u8p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                         i32p]
@@ -167,6 +169,15 @@ def observe_global(state: np.ndarray) -> dict:
     _load().fhpo_observe_global(_u8(state), W, H, out)
     v = list(out)
     return {"mass": v[0], "px": v[1], "py": v[2], "channels": v[3:10], "solid": v[10]}
+
+
+def observe_rows(state: np.ndarray) -> np.ndarray:
+    """int64 (H, 3): (rho, p_x, p_y) summed over each row."""
+    _check_state(state)
+    H, W = state.shape
+    out = np.zeros((H, 3), dtype=np.int64)
+    _load().fhpo_observe_rows(_u8(state), W, H, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return out
 
 
 def observe_blocks(state: np.ndarray, b: int) -> np.ndarray:

@@ -348,6 +348,24 @@ void fhpo_observe_global(const uint8_t *state, uint32_t W, uint32_t H, int64_t o
     }
 }
 
+void fhpo_observe_rows(const uint8_t *state, uint32_t W, uint32_t H, int64_t *out)
+{
+    memset(out, 0, (size_t)H * 3 * sizeof(int64_t));
+    for (uint32_t y = 0; y < H; y++) {
+        int64_t *o = out + (size_t)y * 3;
+        for (uint32_t x = 0; x < W; x++) {
+            uint8_t s = state[(size_t)y * W + x];
+            for (int c = 0; c < 7; c++) {
+                if ((s >> c) & 1) {
+                    o[0] += 1;
+                    o[1] += PX[c];
+                    o[2] += PY[c];
+                }
+            }
+        }
+    }
+}
+
 int fhpo_observe_blocks(const uint8_t *state, uint32_t W, uint32_t H, uint32_t b, int32_t *out)
 {
     if (!state || !out || b == 0) return -1;

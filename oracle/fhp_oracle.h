@@ -108,6 +108,9 @@ int fhpo_run_rules(uint8_t *state, uint8_t *tmp, uint32_t W, uint32_t H, uint64_
 void fhpo_observe_global(const uint8_t *state, uint32_t W, uint32_t H,
                          int64_t out[11]);
 
+/* Row sums: out is int64[H][3] holding (rho, p_x, p_y) of each row. */
+void fhpo_observe_rows(const uint8_t *state, uint32_t W, uint32_t H, int64_t *out);
+
 /* Block sums over b x b blocks in index space: out is
  * int32[ceil(H/b)][ceil(W/b)][3] holding (rho, p_x, p_y). */
 int fhpo_observe_blocks(const uint8_t *state, uint32_t W, uint32_t H,

@@ -20,7 +20,7 @@ OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_BUSY = 0, -1, -2, -3, -4, -5
 WALLS_NONE, WALLS_CHANNEL = 0, 1
 CHIR_HASH, CHIR_ZERO, CHIR_ONE = 0, 1, 2
 RULES_FHP2, RULES_FHP1, RULES_FHP3 = 0, 1, 2
-OBS_GLOBAL, OBS_BLOCKS, OBS_DIGEST = 0, 1, 2
+OBS_GLOBAL, OBS_BLOCKS, OBS_DIGEST, OBS_ROWS = 0, 1, 2, 3
 
 _ERRNAMES = {E_INVAL: "FHP_E_INVAL", E_NOMEM: "FHP_E_NOMEM", E_DEVICE: "FHP_E_DEVICE",
              E_STATE: "FHP_E_STATE", E_BUSY: "FHP_E_BUSY"}

@@ -257,6 +257,23 @@ int fhp_observe(fhp_sim* s, int kind, uint32_t block, void* host_dst, size_t dst
         FHP_HIP_TRY(hipStreamSynchronize(s->st), "sync");
         return FHP_OK;
     }
+    if (kind == FHP_OBS_ROWS) {
+        const size_t row_bytes = 3 * sizeof(int64_t);
+        if (dst_bytes < row_bytes * L.H)
+            return fail(FHP_E_NOMEM, "destination of %zu bytes, %zu needed", dst_bytes,
+                        row_bytes * L.H);
+        int64_t* stage = (int64_t*)s->buf[1 - s->cur];
+        uint32_t rows = (uint32_t)(staging_bytes(s) / row_bytes);
+        if (rows > L.H) rows = L.H;
+        for (uint32_t r0 = 0; r0 < L.H; r0 += rows) {
+            const uint32_t n = (r0 + rows <= L.H) ? rows : L.H - r0;
+            FHP_HIP_TRY(launch_observe_rows(planes, L, r0, n, stage, s->st), "rows");
+            FHP_HIP_TRY(hipMemcpyAsync((char*)host_dst + (size_t)r0 * row_bytes, stage,
+                                       n * row_bytes, hipMemcpyDeviceToHost, s->st), "copy");
+            FHP_HIP_TRY(hipStreamSynchronize(s->st), "sync");
+        }
+        return FHP_OK;
+    }
     if (kind != FHP_OBS_BLOCKS) return fail(FHP_E_INVAL, "unknown observable %d", kind);
     if (block == 0 || (block < 64 ? (64 % block) : (block % 64)))
         return fail(FHP_E_INVAL, "block %u must divide 64 or be a multiple of 64", block);

@@ -69,6 +69,8 @@ hipError_t launch_init(uint64_t* planes, const Lattice& L, uint64_t key_init, ui
 hipError_t launch_or_reduce(const uint64_t* p, size_t n, uint64_t* acc, hipStream_t st);
 hipError_t launch_observe_global(const uint64_t* planes, const Lattice& L, uint64_t* acc,
                                  hipStream_t st);
+hipError_t launch_observe_rows(const uint64_t* planes, const Lattice& L, uint32_t row0,
+                               uint32_t rows, int64_t* out, hipStream_t st);
 hipError_t launch_observe_blocks(const uint64_t* planes, const Lattice& L, uint32_t b,
                                  uint32_t brow0, uint32_t brows, int32_t* out, hipStream_t st);
 hipError_t launch_digest(const uint64_t* planes, const Lattice& L, uint64_t* acc, hipStream_t st);

@@ -171,6 +171,36 @@ __global__ void __launch_bounds__(kBlock) k_observe_blocks(const uint64_t* __res
     dst[2] = py;
 }
 
+// Row sums of (rho, p_x, p_y) for rows row0 .. row0 + rows - 1: one workgroup
+// per row at a time, threads over the row's words, then a workgroup sum.
+__global__ void __launch_bounds__(kBlock) k_observe_rows(const uint64_t* __restrict__ planes,
+                                                         Lattice L, uint32_t row0, uint32_t rows,
+                                                         int64_t* __restrict__ out) {
+    __shared__ int32_t part[3][kBlock / 64];
+    for (uint32_t r = blockIdx.x; r < rows; r += gridDim.x) {
+        const size_t base = (size_t)(row0 + r) * L.wd;
+        int32_t v[3] = {0, 0, 0};
+        for (uint32_t w = threadIdx.x; w < L.wd; w += kBlock)
+            for (int c = 0; c < 7; c++) {
+                const int32_t k = __popcll(planes[(size_t)c * L.ps + base + w]);
+                v[0] += k;
+                v[1] += kPx[c] * k;
+                v[2] += kPy[c] * k;
+            }
+        for (int i = 0; i < 3; i++) {
+            for (int d = 32; d > 0; d >>= 1) v[i] += __shfl_xor(v[i], d);
+            if ((threadIdx.x & 63) == 0) part[i][threadIdx.x >> 6] = v[i];
+        }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            int64_t sum = 0;
+            for (int k = 0; k < kBlock / 64; k++) sum += part[threadIdx.x][k];
+            out[(size_t)r * 3 + threadIdx.x] = sum;
+        }
+        __syncthreads();
+    }
+}
+
 // acc[0] += sum over planes c = 0..7, words (y, w) of H(word, c*2^40 + y*2^20 + w).
 __global__ void __launch_bounds__(kBlock) k_digest(const uint64_t* __restrict__ planes, Lattice L,
                                                    unsigned long long* acc) {
@@ -292,6 +322,14 @@ hipError_t launch_observe_blocks(const uint64_t* planes, const Lattice& L, uint3
     if (!n) return hipSuccess;
     hipLaunchKernelGGL(k_observe_blocks, dim3(grid_for(n)), dim3(kBlock), 0, st, planes, L, b,
                        brow0, brows, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_observe_rows(const uint64_t* planes, const Lattice& L, uint32_t row0,
+                               uint32_t rows, int64_t* out, hipStream_t st) {
+    if (!rows) return hipSuccess;
+    hipLaunchKernelGGL(k_observe_rows, dim3(rows < 4096 ? rows : 4096), dim3(kBlock), 0, st,
+                       planes, L, row0, rows, out);
     return hipGetLastError();
 }
 

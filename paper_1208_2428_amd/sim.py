@@ -101,6 +101,13 @@ class Sim:
         v = [int(x) for x in out]
         return {"mass": v[0], "px": v[1], "py": v[2], "channels": v[3:10], "solid": v[10]}
 
+    def observe_rows(self) -> np.ndarray:
+        """int64 (H, 3): (rho, p_x, p_y) summed over each row."""
+        out = np.zeros((self.height, 3), dtype=np.int64)
+        B.check(self._lib.fhp_observe(self._handle(), B.OBS_ROWS, 0,
+                                      out.ctypes.data_as(ctypes.c_void_p), out.nbytes))
+        return out
+
     def observe_blocks(self, b: int) -> np.ndarray:
         out = np.zeros(((self.height + b - 1) // b, (self.width + b - 1) // b, 3), dtype=np.int32)
         B.check(self._lib.fhp_observe(self._handle(), B.OBS_BLOCKS, int(b),

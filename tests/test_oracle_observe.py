@@ -130,6 +130,28 @@ def test_global_and_block_observables():
         assert blk[by, bx, 1] == int((sub[:6].sum(axis=(1, 2)) * cx).sum())
 
 
+def test_row_observable():
+    rng = np.random.default_rng(2)
+    W, H = 200, 12
+    s = rng.integers(0, 256, (H, W), dtype=np.uint8)
+    rows = oracle.observe_rows(s)
+    assert rows.shape == (H, 3) and rows.dtype == np.int64
+    n = np.stack([(s >> c) & 1 for c in range(7)]).astype(np.int64)
+    ang = np.radians((np.arange(6) - 2) * 60.0)
+    cx = np.round(np.cos(ang) * 2).astype(np.int64)
+    cy = np.round(np.sin(ang) / (math.sqrt(3) / 2)).astype(np.int64)
+    # each row by brute force from the geometry
+    np.testing.assert_array_equal(rows[:, 0], n.sum(axis=(0, 2)))
+    np.testing.assert_array_equal(rows[:, 1], (n[:6].sum(axis=2) * cx[:, None]).sum(axis=0))
+    np.testing.assert_array_equal(rows[:, 2], (n[:6].sum(axis=2) * cy[:, None]).sum(axis=0))
+    # and the rows add up to the global sums and to full-width blocks
+    g = oracle.observe_global(s)
+    assert (int(rows[:, 0].sum()), int(rows[:, 1].sum()), int(rows[:, 2].sum())) == \
+        (g["mass"], g["px"], g["py"])
+    blk = oracle.observe_blocks(s, 1)
+    np.testing.assert_array_equal(rows, blk.sum(axis=1))
+
+
 def test_digest_definition_and_sensitivity():
     rng = np.random.default_rng(1)
     W, H = 256, 6
