@@ -154,8 +154,9 @@ def served_leg(args, wl, mask, value, depth):
     from paper_1208_2428_amd import _binding as B
     from paper_1208_2428_amd import serve
     from paper_1208_2428_amd import workloads as WL
-    depth = min(depth, B.BATCH_MAX_DEPTH)
-    plain = plain_rate(wl, mask, depth, 480)
+    sdepth = min(depth, B.BATCH_MAX_DEPTH)
+    plain = value if sdepth == depth else plain_rate(wl, mask, sdepth, 480)
+    depth = sdepth
     reqs = WL.request_stream(n=args.serve_requests, rate=200.0, seed=5)
     offered = serve.offered_load(reqs)
     log(f"bench: serving {len(reqs)} requests at 200/s (offered {offered:.3e} node-updates/s)")

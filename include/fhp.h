@@ -63,7 +63,8 @@ extern "C" {
 
 #define FHP_ABI_VERSION 1u
 #define FHP_MAX_DEPTH 5u       /* largest temporal-block depth k of one HBM pass */
-#define FHP_BATCH_MAX_DEPTH 4u /* the same for batches and pools */
+#define FHP_BATCH_MAX_DEPTH 5u  /* the same for batches and pools */
+#define FHP_BATCH_MIN_HEIGHT 8u /* shortest lattice a batch or pool takes */
 
 enum {
     FHP_OK = 0,
@@ -183,7 +184,7 @@ void fhp_destroy(fhp_sim *s);
  * two neighbouring bands' previous pass (per-band counters on the device).
  * Each member's results are identical to those of a standalone simulation with
  * the same parameters (Sec. 2 model; the same readings as above).
- * Members need width <= 32768 and height >= 2*FHP_BATCH_MAX_DEPTH.
+ * Members need width <= 32768 and height >= FHP_BATCH_MIN_HEIGHT.
  * ------------------------------------------------------------------------- */
 typedef struct fhp_batch fhp_batch;
 

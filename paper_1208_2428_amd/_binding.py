@@ -14,7 +14,7 @@ from . import build as _build
 
 ABI_VERSION = 1
 MAX_DEPTH = 5
-BATCH_MAX_DEPTH = 4
+BATCH_MAX_DEPTH = 5
 
 OK, E_INVAL, E_NOMEM, E_DEVICE, E_STATE, E_BUSY = 0, -1, -2, -3, -4, -5
 WALLS_NONE, WALLS_CHANNEL = 0, 1

@@ -61,6 +61,11 @@ struct BatchHeader {
 };
 
 constexpr uint32_t kNoLimit = 0xffffffffu;
+// Depth of batches and pools unless set (the deepest; the 512-lattice
+// ensemble measured 14% faster at 5 than at 4).  Members are at least
+// FHP_BATCH_MIN_HEIGHT = 8 >= K rows high, so a band's halo wraps a lattice
+// at most once.
+constexpr uint32_t kBatchDefaultDepth = FHP_BATCH_MAX_DEPTH;
 constexpr uint32_t kSpinLimit = 1u << 24;
 
 __device__ __forceinline__ uint32_t load_acquire(const uint32_t* p) {
@@ -367,6 +372,7 @@ bool pick_kernel(uint32_t K, bool force, bool mask, BatchLaunch* fn, BatchKernel
         case 2: pick<2>(force, mask, fn, kern); return true;
         case 3: pick<3>(force, mask, fn, kern); return true;
         case 4: pick<4>(force, mask, fn, kern); return true;
+        case 5: pick<5>(force, mask, fn, kern); return true;
         default: return false;
     }
 }
@@ -402,7 +408,7 @@ struct Engine {
     uint32_t* done = nullptr;
     uint32_t max_members = 0, max_segs = 0;
     // tiling
-    uint32_t depth = FHP_BATCH_MAX_DEPTH, band = 32, nt_req = 0, passes_per_launch = 1;
+    uint32_t depth = kBatchDefaultDepth, band = 32, nt_req = 0, passes_per_launch = 1;
     int use_graph = 1;
     // current tables
     uint32_t nt = 64, n_groups = 0, n_done = 0, n_members = 0;
@@ -747,9 +753,9 @@ int batch_layout(const fhp_params* ps, uint32_t n, BatchLayout* bl) {
         if (ps[i].width / 64 > kMaxBlockedWords)
             return fail(FHP_E_INVAL, "member %u: width %u above %u", i, ps[i].width,
                         64 * kMaxBlockedWords);
-        if (ps[i].height < 2 * FHP_BATCH_MAX_DEPTH)
+        if (ps[i].height < FHP_BATCH_MIN_HEIGHT)
             return fail(FHP_E_INVAL, "member %u: height %u below %u", i, ps[i].height,
-                        2 * FHP_BATCH_MAX_DEPTH);
+                        FHP_BATCH_MIN_HEIGHT);
         if (ps[i].rules != FHP_RULES_FHP2)
             return fail(FHP_E_INVAL, "member %u: rule set %u; batches run FHP-II only", i,
                         ps[i].rules);
@@ -780,8 +786,8 @@ int pool_check(const fhp_params* p) {
     if (rc) return rc;
     if (p->width / 64 > kMaxBlockedWords)
         return fail(FHP_E_INVAL, "width %u above %u", p->width, 64 * kMaxBlockedWords);
-    if (p->height < 2 * FHP_BATCH_MAX_DEPTH)
-        return fail(FHP_E_INVAL, "height %u below %u", p->height, 2 * FHP_BATCH_MAX_DEPTH);
+    if (p->height < FHP_BATCH_MIN_HEIGHT)
+        return fail(FHP_E_INVAL, "height %u below %u", p->height, FHP_BATCH_MIN_HEIGHT);
     if (p->rules != FHP_RULES_FHP2)
         return fail(FHP_E_INVAL, "rule set %u: batches and pools run FHP-II only", p->rules);
     return FHP_OK;
@@ -849,7 +855,7 @@ int fhp_batch_set_tiling(fhp_batch* b, uint32_t depth, uint32_t band, uint32_t g
     if (depth > FHP_BATCH_MAX_DEPTH) return fail(FHP_E_INVAL, "depth %u above %u", depth, FHP_BATCH_MAX_DEPTH);
     if (group_threads % 64 || group_threads > 512)
         return fail(FHP_E_INVAL, "group_threads %u: a multiple of 64 up to 512", group_threads);
-    b->eng.depth = depth ? depth : FHP_BATCH_MAX_DEPTH;
+    b->eng.depth = depth ? depth : kBatchDefaultDepth;
     b->eng.band = band ? band : 32;
     b->eng.nt_req = group_threads;
     b->eng.passes_per_launch = passes_per_launch;
@@ -949,7 +955,7 @@ int fhp_pool_set_tiling(fhp_pool* pl, uint32_t depth, uint32_t band, uint32_t gr
         return fail(FHP_E_INVAL, "group_threads %u: a multiple of 64 up to 512", group_threads);
     for (auto& s : pl->slots)
         if (s.used) return fail(FHP_E_STATE, "tiling can change only while the pool is empty");
-    pl->eng.depth = depth ? depth : FHP_BATCH_MAX_DEPTH;
+    pl->eng.depth = depth ? depth : kBatchDefaultDepth;
     pl->eng.band = band ? band : 32;
     pl->eng.nt_req = group_threads;
     return FHP_OK;

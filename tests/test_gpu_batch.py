@@ -42,7 +42,8 @@ def oracle_state(kw, steps):
 
 @pytest.mark.parametrize("depth,ppl,threads,graph", [
     (1, 1, 0, True), (2, 1, 0, True), (3, 1, 128, False), (4, 1, 0, True),
-    (2, 0, 0, True), (3, 0, 256, True), (4, 0, 64, False), (3, 2, 0, True)])
+    (2, 0, 0, True), (3, 0, 256, True), (4, 0, 64, False), (3, 2, 0, True),
+    (5, 1, 0, True), (5, 0, 128, True), (5, 2, 64, False)])
 def test_mixed_batch_matches_oracle(depth, ppl, threads, graph):
     say("batch", depth, ppl, threads, graph)
     params = mixed_params()

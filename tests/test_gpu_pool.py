@@ -29,9 +29,10 @@ def oracle_state(p, steps):
     return st
 
 
-def test_jobs_same_alone_and_in_the_mix():
+@pytest.mark.parametrize("depth", [4, 5])
+def test_jobs_same_alone_and_in_the_mix(depth):
     pool = Pool(Pool.arena_bytes_for(16, 4096, 64 << 20), max_slots=16, max_bands=4096,
-                group_threads=128)
+                group_threads=128, depth=depth)
     jobs = [
         (dict(width=256, height=256, seed=11, fill=0.25, force_rate=1e-3, walls=True), 37),
         (dict(width=128, height=64, seed=12, fill=0.3), 9),
