@@ -93,12 +93,11 @@ Layout layout_for(uint32_t W, uint32_t H) {
 }
 
 // Default temporal-block depth where the blocked kernel applies (full-row
-// workgroups, at most kMaxBlockedWords words per row).  On the 16384^2 porous
-// lattice four steps per pass are fastest: the pass is then bound by VALU
-// work rather than by HBM traffic.
-// Depth 5 is the deepest whose register queue fits without spilling (5% fewer
-// HBM bytes per step than depth 4 for 3% more halo work; measured 3-4% faster
-// on a 16384^2 lattice).
+// workgroups, at most kMaxBlockedWords words per row): the deepest whose
+// register queue fits without spilling.  On the 16384^2 porous lattice the
+// pass is then bound by VALU work rather than by HBM traffic; depth 5 moves
+// 18% fewer HBM bytes per step than depth 4 for 3% more halo work and
+// measured 3-4% faster.
 uint32_t default_depth(uint32_t wd) { return wd <= kMaxBlockedWords ? FHP_MAX_DEPTH : 1; }
 
 // Default band height of the blocked kernel: 32 rows balances the halo rows
