@@ -111,7 +111,7 @@ typedef struct fhp_params {
     uint32_t height;      /* H: even, >= 2, < 2^20; W*H < 2^35 */
     uint32_t walls;       /* FHP_WALLS_* */
     uint32_t chirality;   /* FHP_CHIR_*; ZERO and ONE are test modes */
-    uint32_t rules;       /* FHP_RULES_*; 0 = FHP-II (batches and pools take FHP-II only) */
+    uint32_t rules;       /* FHP_RULES_*; 0 = FHP-II */
     uint64_t seed;
     double fill;          /* per-channel occupancy of fluid nodes at t = 0, in [0, 1] */
     double force_rate;    /* forcing coin rate f per node and step, in [0, 1/64) */
@@ -184,7 +184,9 @@ void fhp_destroy(fhp_sim *s);
  * two neighbouring bands' previous pass (per-band counters on the device).
  * Each member's results are identical to those of a standalone simulation with
  * the same parameters (Sec. 2 model; the same readings as above).
- * Members need width <= 32768 and height >= FHP_BATCH_MIN_HEIGHT.
+ * Members need width <= 32768 and height >= FHP_BATCH_MIN_HEIGHT, and all
+ * members share one rule set (FHP_RULES_FHP3 batches run passes of at most 3
+ * steps).
  * ------------------------------------------------------------------------- */
 typedef struct fhp_batch fhp_batch;
 
@@ -253,6 +255,11 @@ int fhp_pool_create(void *dev_arena, size_t arena_bytes, uint32_t max_slots, uin
  * (0 = smallest that holds the widest row) of the pool's launches; only while
  * the pool is empty. */
 int fhp_pool_set_tiling(fhp_pool *pl, uint32_t depth, uint32_t band, uint32_t group_threads);
+
+/* Rule set (FHP_RULES_*) of every job of the pool, FHP-II until set; only
+ * while the pool is empty.  fhp_pool_admit rejects jobs of another rule set
+ * with FHP_E_INVAL. */
+int fhp_pool_set_rules(fhp_pool *pl, uint32_t rules);
 
 /* Admits a job: creates the lattice of *p at t = 0 in the arena and schedules
  * `steps` steps.  FHP_E_BUSY when no slot, memory or band room is free (the

@@ -84,6 +84,7 @@ _SIGNATURES = {
     "fhp_pool_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_size_t, ctypes.c_uint32,
                                        ctypes.c_uint32, ctypes.c_void_p,
                                        ctypes.POINTER(ctypes.c_void_p)]),
+    "fhp_pool_set_rules": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     "fhp_pool_set_tiling": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                            ctypes.c_uint32]),
     "fhp_pool_admit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Params), ctypes.c_uint64,

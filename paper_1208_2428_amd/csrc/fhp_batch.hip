@@ -78,7 +78,7 @@ __device__ __forceinline__ uint64_t uni(uint64_t v) {
     return ((uint64_t)uni((uint32_t)(v >> 32)) << 32) | uni((uint32_t)v);
 }
 
-template <int K, bool FORCE, bool MASK>
+template <int K, bool FORCE, bool MASK, int RULES>
 __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
                                                MemberDesc* __restrict__ members,
                                                const GroupDesc* __restrict__ groups,
@@ -260,7 +260,7 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
                 const uint64_t chi = (mix64(zc) & chi_and) | chi_or;
                 const uint64_t coin = FORCE ? coin_word(mix64(zf), thr) : 0ull;
                 Row Y;
-                update(n, sw, chi, coin, Y.p);
+                update<RULES>(n, sw, chi, coin, Y.p);
                 Y.s = sw;
                 push(lc, X);
                 if (l < K) {
@@ -336,11 +336,11 @@ __global__ void k_batch_header(BatchHeader* hdr, uint32_t passes, uint32_t K) {
     hdr->K = K;
 }
 
-template <int K, bool FORCE, bool MASK>
+template <int K, bool FORCE, bool MASK, int RULES>
 hipError_t launch_batch_t(BatchHeader* hdr, MemberDesc* members, const GroupDesc* groups,
                           const WaveDesc* waves, uint32_t* done, uint32_t grid, uint32_t nt,
                           hipStream_t st) {
-    hipLaunchKernelGGL((k_batch<K, FORCE, MASK>), dim3(grid), dim3(nt),
+    hipLaunchKernelGGL((k_batch<K, FORCE, MASK, RULES>), dim3(grid), dim3(nt),
                        (2 * nt + 1) * sizeof(uint32_t), st, hdr, members, groups, waves, done);
     return hipGetLastError();
 }
@@ -349,32 +349,53 @@ using BatchLaunch = hipError_t (*)(BatchHeader*, MemberDesc*, const GroupDesc*, 
                                    uint32_t*, uint32_t, uint32_t, hipStream_t);
 using BatchKernel = const void*;
 
+template <int K, bool FORCE, bool MASK, int RULES>
+void pick_one(BatchLaunch* fn, BatchKernel* kern) {
+    *fn = launch_batch_t<K, FORCE, MASK, RULES>;
+    *kern = (const void*)k_batch<K, FORCE, MASK, RULES>;
+}
+
+// FHP-II has a kernel for every combination of forcing and obstacles; the
+// other rule sets use the forcing variant (a zero rate draws no coin), and
+// FHP-III runs at most kMaxDepthFHP3 steps per pass.
 template <int K>
-void pick(bool force, bool mask, BatchLaunch* fn, BatchKernel* kern) {
-    if (force && mask) {
-        *fn = launch_batch_t<K, true, true>;
-        *kern = (const void*)k_batch<K, true, true>;
-    } else if (force) {
-        *fn = launch_batch_t<K, true, false>;
-        *kern = (const void*)k_batch<K, true, false>;
-    } else if (mask) {
-        *fn = launch_batch_t<K, false, true>;
-        *kern = (const void*)k_batch<K, false, true>;
-    } else {
-        *fn = launch_batch_t<K, false, false>;
-        *kern = (const void*)k_batch<K, false, false>;
+bool pick(bool force, bool mask, uint32_t rules, BatchLaunch* fn, BatchKernel* kern) {
+    if (rules == kRulesFHP1) {
+        if (mask) pick_one<K, true, true, kRulesFHP1>(fn, kern);
+        else pick_one<K, true, false, kRulesFHP1>(fn, kern);
+        return true;
+    }
+    if (rules == kRulesFHP3) {
+        if constexpr (K <= kMaxDepthFHP3) {
+            if (mask) pick_one<K, true, true, kRulesFHP3>(fn, kern);
+            else pick_one<K, true, false, kRulesFHP3>(fn, kern);
+            return true;
+        }
+        return false;
+    }
+    if (force && mask) pick_one<K, true, true, kRulesFHP2>(fn, kern);
+    else if (force) pick_one<K, true, false, kRulesFHP2>(fn, kern);
+    else if (mask) pick_one<K, false, true, kRulesFHP2>(fn, kern);
+    else pick_one<K, false, false, kRulesFHP2>(fn, kern);
+    return true;
+}
+
+bool pick_kernel(uint32_t K, bool force, bool mask, uint32_t rules, BatchLaunch* fn,
+                 BatchKernel* kern) {
+    switch (K) {
+        case 1: return pick<1>(force, mask, rules, fn, kern);
+        case 2: return pick<2>(force, mask, rules, fn, kern);
+        case 3: return pick<3>(force, mask, rules, fn, kern);
+        case 4: return pick<4>(force, mask, rules, fn, kern);
+        case 5: return pick<5>(force, mask, rules, fn, kern);
+        default: return false;
     }
 }
 
-bool pick_kernel(uint32_t K, bool force, bool mask, BatchLaunch* fn, BatchKernel* kern) {
-    switch (K) {
-        case 1: pick<1>(force, mask, fn, kern); return true;
-        case 2: pick<2>(force, mask, fn, kern); return true;
-        case 3: pick<3>(force, mask, fn, kern); return true;
-        case 4: pick<4>(force, mask, fn, kern); return true;
-        case 5: pick<5>(force, mask, fn, kern); return true;
-        default: return false;
-    }
+// Steps per pass for a requested depth: FHP-III passes are at most
+// kMaxDepthFHP3 deep.
+uint32_t effective_depth(uint32_t depth, uint32_t rules) {
+    return (rules == FHP_RULES_FHP3 && depth > kMaxDepthFHP3) ? kMaxDepthFHP3 : depth;
 }
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -409,6 +430,8 @@ struct Engine {
     uint32_t max_members = 0, max_segs = 0;
     // tiling
     uint32_t depth = kBatchDefaultDepth, band = 32, nt_req = 0, passes_per_launch = 1;
+    uint32_t depth_req = kBatchDefaultDepth;  // depth asked for; depth = its effective value
+    uint32_t rules = FHP_RULES_FHP2;          // rule set of every member
     int use_graph = 1;
     // current tables
     uint32_t nt = 64, n_groups = 0, n_done = 0, n_members = 0;
@@ -421,6 +444,7 @@ struct Engine {
     hipGraphExec_t graph = nullptr;
     uint32_t g_K = 0, g_passes = 0, g_launches = 0, g_nt = 0, g_grid = 0;
     bool g_force = false, g_mask = false;
+    uint32_t g_rules = 0;
 };
 
 // Device table space for up to `members` lattices and `segs` bands: header,
@@ -561,10 +585,11 @@ int engine_build(Engine* e, fhp_sim* const* sims, const uint32_t* limit, uint32_
 }
 
 // Persistent grid: every workgroup that fits on the device at once.
-int engine_grid(uint32_t K, bool force, bool mask, uint32_t nt, uint32_t* grid) {
+int engine_grid(uint32_t K, bool force, bool mask, uint32_t rules, uint32_t nt, uint32_t* grid) {
     BatchLaunch fn;
     BatchKernel kern;
-    if (!pick_kernel(K, force, mask, &fn, &kern)) return fail(FHP_E_INVAL, "depth %u", K);
+    if (!pick_kernel(K, force, mask, rules, &fn, &kern))
+        return fail(FHP_E_INVAL, "depth %u, rule set %u", K, rules);
     int per_cu = 0, dev = 0, cus = 0;
     FHP_HIP_TRY(hipGetDevice(&dev), "device");
     FHP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "attr");
@@ -577,8 +602,9 @@ int engine_grid(uint32_t K, bool force, bool mask, uint32_t nt, uint32_t* grid) 
 
 int engine_kernel(Engine* e, uint32_t K, BatchLaunch* fn, uint32_t* grid) {
     BatchKernel kern;
-    if (!pick_kernel(K, e->force, e->mask, fn, &kern)) return fail(FHP_E_INVAL, "depth %u", K);
-    return engine_grid(K, e->force, e->mask, e->nt, grid);
+    if (!pick_kernel(K, e->force, e->mask, e->rules, fn, &kern))
+        return fail(FHP_E_INVAL, "depth %u, rule set %u", K, e->rules);
+    return engine_grid(K, e->force, e->mask, e->rules, e->nt, grid);
 }
 
 int engine_enqueue(Engine* e, uint32_t K, uint32_t passes, uint32_t launches) {
@@ -604,7 +630,8 @@ int engine_run(Engine* e, uint32_t K, uint32_t passes, uint32_t launches) {
     int rc = engine_kernel(e, K, &fn, &grid);
     if (rc) return rc;
     if (!e->graph || e->g_K != K || e->g_passes != passes || e->g_launches != launches ||
-        e->g_nt != e->nt || e->g_grid != grid || e->g_force != e->force || e->g_mask != e->mask) {
+        e->g_nt != e->nt || e->g_grid != grid || e->g_force != e->force || e->g_mask != e->mask ||
+        e->g_rules != e->rules) {
         if (e->graph) {
             (void)hipGraphExecDestroy(e->graph);
             e->graph = nullptr;
@@ -631,6 +658,7 @@ int engine_run(Engine* e, uint32_t K, uint32_t passes, uint32_t launches) {
         e->g_grid = grid;
         e->g_force = e->force;
         e->g_mask = e->mask;
+        e->g_rules = e->rules;
     }
     FHP_HIP_TRY(hipGraphLaunch(e->graph, e->st), "graph launch");
     return FHP_OK;
@@ -756,9 +784,9 @@ int batch_layout(const fhp_params* ps, uint32_t n, BatchLayout* bl) {
         if (ps[i].height < FHP_BATCH_MIN_HEIGHT)
             return fail(FHP_E_INVAL, "member %u: height %u below %u", i, ps[i].height,
                         FHP_BATCH_MIN_HEIGHT);
-        if (ps[i].rules != FHP_RULES_FHP2)
-            return fail(FHP_E_INVAL, "member %u: rule set %u; batches run FHP-II only", i,
-                        ps[i].rules);
+        if (ps[i].rules != ps[0].rules)
+            return fail(FHP_E_INVAL, "member %u: rule set %u, member 0 has %u; a batch runs one",
+                        i, ps[i].rules, ps[0].rules);
         bl->member_off[i] = off;
         off += round_up(layout_for(ps[i].width, ps[i].height).aux_off, 32);  // planes and S
         segs += ps[i].height / 2;  // bands of at least 2 rows
@@ -788,8 +816,6 @@ int pool_check(const fhp_params* p) {
         return fail(FHP_E_INVAL, "width %u above %u", p->width, 64 * kMaxBlockedWords);
     if (p->height < FHP_BATCH_MIN_HEIGHT)
         return fail(FHP_E_INVAL, "height %u below %u", p->height, FHP_BATCH_MIN_HEIGHT);
-    if (p->rules != FHP_RULES_FHP2)
-        return fail(FHP_E_INVAL, "rule set %u: batches and pools run FHP-II only", p->rules);
     return FHP_OK;
 }
 
@@ -831,6 +857,8 @@ int fhp_batch_create(const fhp_params* ps, uint32_t n, void* dev_ws, size_t ws_b
     b->n = n;
     b->aux = ws + bl.aux_off;
     rc = engine_init(&b->eng, ws + bl.tables_off, n, (uint32_t)bl.max_segs, st);
+    b->eng.rules = ps[0].rules;
+    b->eng.depth = effective_depth(b->eng.depth_req, b->eng.rules);
     for (uint32_t i = 0; i < n && !rc; i++) {
         const Layout lay = layout_for(ps[i].width, ps[i].height);
         rc = sim_setup(&b->sims[i], &ps[i], ws + bl.member_off[i], lay, b->aux, st);
@@ -855,7 +883,8 @@ int fhp_batch_set_tiling(fhp_batch* b, uint32_t depth, uint32_t band, uint32_t g
     if (depth > FHP_BATCH_MAX_DEPTH) return fail(FHP_E_INVAL, "depth %u above %u", depth, FHP_BATCH_MAX_DEPTH);
     if (group_threads % 64 || group_threads > 512)
         return fail(FHP_E_INVAL, "group_threads %u: a multiple of 64 up to 512", group_threads);
-    b->eng.depth = depth ? depth : kBatchDefaultDepth;
+    b->eng.depth_req = depth ? depth : kBatchDefaultDepth;
+    b->eng.depth = effective_depth(b->eng.depth_req, b->eng.rules);
     b->eng.band = band ? band : 32;
     b->eng.nt_req = group_threads;
     b->eng.passes_per_launch = passes_per_launch;
@@ -955,9 +984,20 @@ int fhp_pool_set_tiling(fhp_pool* pl, uint32_t depth, uint32_t band, uint32_t gr
         return fail(FHP_E_INVAL, "group_threads %u: a multiple of 64 up to 512", group_threads);
     for (auto& s : pl->slots)
         if (s.used) return fail(FHP_E_STATE, "tiling can change only while the pool is empty");
-    pl->eng.depth = depth ? depth : kBatchDefaultDepth;
+    pl->eng.depth_req = depth ? depth : kBatchDefaultDepth;
+    pl->eng.depth = effective_depth(pl->eng.depth_req, pl->eng.rules);
     pl->eng.band = band ? band : 32;
     pl->eng.nt_req = group_threads;
+    return FHP_OK;
+}
+
+int fhp_pool_set_rules(fhp_pool* pl, uint32_t rules) {
+    if (!pl) return fail(FHP_E_INVAL, "pool is NULL");
+    if (rules > FHP_RULES_FHP3) return fail(FHP_E_INVAL, "rule set %u unknown", rules);
+    for (auto& s : pl->slots)
+        if (s.used) return fail(FHP_E_STATE, "the rule set can change only while the pool is empty");
+    pl->eng.rules = rules;
+    pl->eng.depth = effective_depth(pl->eng.depth_req, rules);
     return FHP_OK;
 }
 
@@ -965,6 +1005,9 @@ int fhp_pool_admit(fhp_pool* pl, const fhp_params* p, uint64_t steps, uint32_t* 
     if (!pl || !slot) return fail(FHP_E_INVAL, "NULL argument");
     int rc = pool_check(p);
     if (rc) return rc;
+    if (p->rules != pl->eng.rules)
+        return fail(FHP_E_INVAL, "rule set %u: this pool runs rule set %u (fhp_pool_set_rules)",
+                    p->rules, pl->eng.rules);
     if (steps >= kTimeLimit) return fail(FHP_E_STATE, "%llu steps: time would reach 2^24",
                                          (unsigned long long)steps);
     uint32_t i = 0;

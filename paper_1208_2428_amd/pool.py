@@ -18,7 +18,7 @@ class Pool:
 
     def __init__(self, arena_bytes: int, max_slots: int = 256, max_bands: int = 1 << 16,
                  device=None, stream=None, depth: int = 0, band: int = 0,
-                 group_threads: int = 0):
+                 group_threads: int = 0, rules: int = B.RULES_FHP2):
         lib = B.load()
         if not torch.cuda.is_available():
             raise RuntimeError("the FHP library needs a ROCm GPU (torch.cuda is unavailable)")
@@ -37,6 +37,8 @@ class Pool:
         self._pinned = {}
         if depth or band or group_threads:
             B.check(lib.fhp_pool_set_tiling(h, int(depth), int(band), int(group_threads)))
+        if rules != B.RULES_FHP2:
+            B.check(lib.fhp_pool_set_rules(h, int(rules)))
 
     @staticmethod
     def arena_bytes_for(max_slots: int, max_bands: int, lattice_bytes: int) -> int:
@@ -56,6 +58,10 @@ class Pool:
         B.check(rc)
         self._shapes[int(slot.value)] = (params["width"], params["height"])
         return int(slot.value)
+
+    def set_rules(self, rules: int) -> None:
+        """Rule set of every job (FHP-II until set); only while the pool is empty."""
+        B.check(self._lib.fhp_pool_set_rules(self._h, int(rules)))
 
     def tick(self, passes: int = 1) -> None:
         B.check(self._lib.fhp_pool_tick(self._h, int(passes)))

@@ -113,8 +113,12 @@ def test_rule_set_checks(lib):
         assert lib.fhp_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == B.OK
     p, _ = B.make_params(128, 64, rules=3)
     assert lib.fhp_workspace_bytes(ctypes.byref(p), ctypes.byref(n)) == B.E_INVAL
-    # batches and pools run FHP-II only, and say so before touching the device
-    arr = (B.Params * 1)()
+    # a batch runs one rule set: any one, not a mix (checked before the device)
+    arr = (B.Params * 2)()
     arr[0], _ = B.make_params(128, 64, rules=B.RULES_FHP3)
-    assert lib.fhp_batch_workspace_bytes(arr, 1, ctypes.byref(n)) == B.E_INVAL
-    assert b"FHP-II" in lib.fhp_last_error()
+    arr[1], _ = B.make_params(256, 32, rules=B.RULES_FHP3)
+    assert lib.fhp_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == B.OK
+    arr[1], _ = B.make_params(256, 32, rules=B.RULES_FHP1)
+    assert lib.fhp_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == B.E_INVAL
+    assert b"rule set" in lib.fhp_last_error()
+    assert lib.fhp_pool_set_rules(None, B.RULES_FHP1) == B.E_INVAL

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1208_2428_amd import Pool, Sim
+from paper_1208_2428_amd import Batch, Pool, Sim
 from paper_1208_2428_amd import _binding as B
 from paper_1208_2428_amd import workloads as WL
 
@@ -86,8 +86,65 @@ def test_rule_sets_differ_and_conserve():
     assert not np.array_equal(out[B.RULES_FHP2], out[B.RULES_FHP3])
 
 
-def test_pool_rejects_other_rule_sets():
-    pool = Pool(Pool.arena_bytes_for(2, 64, 8 << 20), max_slots=2, max_bands=64)
-    with pytest.raises(RuntimeError, match="FHP-II"):
-        pool.admit(4, width=128, height=32, seed=1, fill=0.2, rules=B.RULES_FHP1)
+def mixed(rules):
+    mask = WL.porous_mask(192, 64, seed=9, rmin=3, rmax=6, frac=0.08)
+    return [
+        dict(width=64, height=8, seed=1, fill=0.45, rules=rules),
+        dict(width=128, height=128, seed=2, fill=0.5, force_rate=1e-2, walls=True, rules=rules),
+        dict(width=192, height=64, seed=3, fill=0.4, solid=mask, rules=rules),
+        dict(width=320, height=96, seed=5, fill=0.6, force_rate=5e-3, rules=rules),
+        dict(width=1024, height=40, seed=8, fill=0.5, walls=True, rules=rules),
+        dict(width=64, height=10, seed=9, fill=0.5, chirality=2, rules=rules),
+    ]
+
+
+def oracle_member(kw, steps, oracle_rules):
+    st = oracle.init(kw["width"], kw["height"], kw["seed"], kw["fill"], mask=kw.get("solid"),
+                     walls=kw.get("walls", False))
+    st, _ = oracle.run(st, 0, steps, kw["seed"], kw.get("force_rate", 0.0),
+                       chir_mode=kw.get("chirality", 0), threads=THREADS, rules=oracle_rules)
+    return st
+
+
+@pytest.mark.parametrize("name", list(RULES))
+@pytest.mark.parametrize("depth,ppl", [(5, 1), (3, 0), (2, 2)])
+def test_batch_of_a_rule_set_matches_oracle(name, depth, ppl):
+    say("batch rules", name, depth, ppl)
+    gpu_rules, oracle_rules = RULES[name]
+    params = mixed(gpu_rules)
+    b = Batch(params, depth=depth, passes_per_launch=ppl)
+    steps = 0
+    for n in (12, 5, 7):
+        b.step(n)
+        steps += n
+        b.sync()
+        for i, kw in enumerate(params):
+            np.testing.assert_array_equal(b[i].get_state(), oracle_member(kw, steps, oracle_rules),
+                                          err_msg=f"{name} member {i} after {steps} steps")
+    b.close()
+
+
+@pytest.mark.parametrize("name", list(RULES))
+def test_pool_of_a_rule_set(name):
+    gpu_rules, oracle_rules = RULES[name]
+    pool = Pool(Pool.arena_bytes_for(8, 4096, 32 << 20), max_slots=8, max_bands=4096,
+                rules=gpu_rules)
+    # jobs of another rule set are refused
+    with pytest.raises(RuntimeError, match="rule set"):
+        pool.admit(4, width=128, height=32, seed=1, fill=0.2)
+    jobs = [(dict(width=256, height=64, seed=21, fill=0.5, force_rate=1e-3, walls=True,
+                  rules=gpu_rules), 23),
+            (dict(width=128, height=40, seed=22, fill=0.4, rules=gpu_rules), 9)]
+    slots = {pool.admit(n, **p): k for k, (p, n) in enumerate(jobs)}
+    # the rule set changes only while the pool is empty
+    with pytest.raises(RuntimeError, match="empty"):
+        pool.set_rules(B.RULES_FHP2)
+    got = {}
+    while len(got) < len(jobs):
+        pool.tick(2)
+        for s in pool.done():
+            got[slots[s]] = pool.member(s).get_state()
+            pool.release(s)
+    for k, (p, n) in enumerate(jobs):
+        np.testing.assert_array_equal(got[k], oracle_member(p, n, oracle_rules), err_msg=str(k))
     pool.close()
