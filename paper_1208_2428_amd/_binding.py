@@ -123,6 +123,11 @@ def load():
         raise RuntimeError(
             f"{path} is missing: build the HIP library first "
             "(python -c 'import __graft_entry__ as g; g.build()')")
+    # torch ships its own HIP runtime under the same soname (libamdhip64.so.7)
+    # as the system one the library links; whichever is loaded first serves
+    # the whole process.  Loading torch first keeps the library on the runtime
+    # that owns torch's device memory and streams.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGNATURES.items():
         fn = getattr(lib, name)

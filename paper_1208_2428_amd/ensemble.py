@@ -63,3 +63,24 @@ def run_one_by_one(params: list[dict], steps: int, depth: int = 0) -> dict:
     for s in sims:
         s.close()
     return {"value": nodes * steps / wall, "unit": "node-updates/s", "seconds": wall}
+
+
+def main(argv=None) -> int:
+    """python -m paper_1208_2428_amd.ensemble [--steps N] [--depth K] [--band T]
+    [--threads NT]: times the 512-lattice ensemble at a fixed tiling."""
+    import argparse
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--depth", type=int, default=5)
+    ap.add_argument("--band", type=int, default=32)
+    ap.add_argument("--threads", type=int, default=64)
+    a = ap.parse_args(argv)
+    tiling = dict(depth=a.depth, band=a.band, group_threads=a.threads, passes_per_launch=1)
+    r = run_batched(ensemble_params(), a.steps, tiling)
+    print(f"ensemble: {r['lattices']} lattices, {r['nodes']} nodes, {a.steps} steps, tiling {tiling}: "
+          f"{r['value']:.3e} node-updates/s ({r['seconds'] * 1e3:.1f} ms)", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
