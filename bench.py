@@ -75,6 +75,37 @@ def cpu_baseline(wl, mask, seconds: float):
                       f"{steps} steps in {el:.1f} s"}
 
 
+VALU_WAVE_INSTR_PEAK = 256 * 4 * 2.4e9 / 4  # SIMDs x clock / 4 cycles per wave64 instruction
+
+
+def recorded_valu(name: str, depth: int):
+    """VALU instructions per launch (all waves) from the rocprofv3 SQ_INSTS_VALU
+    pass recorded under profiles/, if it was taken on these kernel sources at
+    this depth."""
+    from paper_1208_2428_amd import profsum
+    path = os.path.join(ROOT, "profiles", f"k_stepk_{name}.md")
+    _, src, rec_depth = profsum.recorded_traffic(path)
+    insts = profsum.recorded_value(path, "valu_insts_per_launch")
+    if insts is None or depth != rec_depth or src != profsum.kernel_source_hash():
+        return None
+    return insts
+
+
+def depth_sweep(wl, mask, steps: int):
+    """Throughput and HBM roofline fraction of the single-lattice kernel at
+    every depth (the fraction of 14/K bits per node-step falls with K by
+    construction; the HBM-bound regime is K <= 2)."""
+    from paper_1208_2428_amd import _binding as B
+    out = []
+    for k in range(1, B.MAX_DEPTH + 1):
+        n = steps - steps % k
+        v = plain_rate(wl, mask, k, n)
+        frac = v * PLANE_BITS / k / 8 / 1e9 / HBM_PEAK_GBS
+        out.append({"depth": k, "value": v, "frac": frac, "steps": n})
+        log(f"bench: depth {k}: {v:.3e} node-updates/s, {frac:.3f} of the HBM roofline")
+    return out
+
+
 def plain_rate(wl, mask, depth: int, steps: int) -> float:
     """Node updates/s of the single-lattice kernel at depth `depth`."""
     import torch
@@ -200,6 +231,9 @@ def main() -> int:
     ap.add_argument("--no-rules", action="store_true",
                     help="skip the FHP-I / FHP-III rule-set leg")
     ap.add_argument("--rules-steps", type=int, default=400)
+    ap.add_argument("--no-depth-sweep", action="store_true",
+                    help="skip the throughput / roofline sweep over depths 1..5")
+    ap.add_argument("--sweep-steps", type=int, default=240)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -258,6 +292,7 @@ def main() -> int:
     achieved = bytes_per_launch / launch_s / 1e9
     sim.close()
     traffic = recorded_traffic(wl.name, depth)
+    valu = recorded_valu(wl.name, depth)
 
     value = nodes * args.steps / wall
     out = {
@@ -281,6 +316,15 @@ def main() -> int:
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel_us": launch_s * 1e6, "bytes_per_launch": bytes_per_launch},
     }
+    if valu is not None:
+        # the same launch against the VALU issue limit (wave64 instructions;
+        # quarter-rate multiplies, 7% of them, count once here)
+        rate = valu / launch_s
+        out["alu"] = {"bound": "alu", "achieved": rate, "peak": VALU_WAVE_INSTR_PEAK,
+                      "unit": "wave64 VALU instructions/s", "frac": rate / VALU_WAVE_INSTR_PEAK,
+                      "valu_insts_per_launch": valu}
+    if not args.no_depth_sweep:
+        out["depth_sweep"] = depth_sweep(wl, mask, args.sweep_steps)
     if not args.no_ensemble:
         out["batched"] = batched_leg(args, wl, mask, depth, value)
     if not args.no_serve:

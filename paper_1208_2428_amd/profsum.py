@@ -55,6 +55,16 @@ def pmc_summary(path: str, match: str | None = None) -> dict:
     return {k: (len(v), sum(v) / len(v)) for k, v in acc.items()}
 
 
+def recorded_value(profile_md: str, key: str) -> float | None:
+    """A `key: number` line of a profiles/ note, or None."""
+    try:
+        text = open(profile_md).read()
+    except OSError:
+        return None
+    m = re.search(re.escape(key) + r":\s*([0-9.eE+]+)", text)
+    return float(m.group(1)) if m else None
+
+
 def recorded_traffic(profile_md: str) -> tuple[float | None, str | None, int | None]:
     """(bytes per launch, kernel source hash, depth) recorded in a profiles/ note."""
     try:
