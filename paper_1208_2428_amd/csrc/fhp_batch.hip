@@ -84,11 +84,11 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
                                                const GroupDesc* __restrict__ groups,
                                                const WaveDesc* __restrict__ waves,
                                                uint32_t* __restrict__ done) {
-    extern __shared__ uint32_t xch[];  // 2 carry slots x nt, then one broadcast word
+    extern __shared__ uint4 xch[];  // 2 carry slots x nt entries, then one broadcast word
     const uint32_t nt = blockDim.x;
     const uint32_t lane = threadIdx.x;
     const uint32_t wave = uni(lane >> 6);
-    uint32_t* bcast = xch + 2 * nt;
+    uint32_t* bcast = reinterpret_cast<uint32_t*>(xch + 2 * nt);
     const uint32_t n_groups = hdr->n_groups;
     const uint32_t passes = hdr->passes;
     const uint32_t n_items = n_groups * passes;
@@ -200,16 +200,18 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
         };
 
         uint64_t a3[K + 1], a4[K + 1], bp[K + 1][7], bs[K + 1];
-        uint32_t ac[K + 1], bc[K + 1];
+        uint32_t ac[K + 1], b2[K + 1], b5[K + 1], bq[K + 1];
         auto push = [&](auto lc, const Row& x) __attribute__((always_inline)) {
             constexpr int l = decltype(lc)::value;
             a3[l] = bp[l][3];
             a4[l] = bp[l][4];
-            ac[l] = bc[l];
+            ac[l] = bq[l];
 #pragma unroll
             for (int c = 0; c < 7; c++) bp[l][c] = x.p[c];
             bs[l] = x.s;
-            bc[l] = x.c;
+            b2[l] = x.c[1];
+            b5[l] = x.c[2];
+            bq[l] = x.c[3];
         };
         Row nxt;
         load(-K, nxt);
@@ -228,7 +230,7 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
                 else if (d0 == (int)T - 1 || d0 == (int)T) s = bot ? ~0ull : s;
             }
             X.s = s;
-            exchange(xch, slot, nt, lane, wl, wr, X);
+            exchange<((PAR + K) & 1) != 0>(xch, slot, nt, lane, wl, wr, X);  // y0 even: parity of y
             bool have = true;
             static_for<1, K>([&](auto lc) __attribute__((always_inline)) {
                 constexpr int l = decltype(lc)::value;
@@ -243,7 +245,7 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
                 const int dl = d0 - l;  // row of this level, relative to y0
                 constexpr bool odd = ((PAR + K + l) & 1) != 0;  // y0 even: parity of the row
                 uint64_t n[7];
-                stream_in<odd>(a3[l], a4[l], ac[l], bp[l], bc[l], X, n);
+                stream_in<odd>(a3[l], a4[l], ac[l], bp[l], b2[l], b5[l], X, n);
                 const uint64_t sw = bs[l];
                 uint64_t dz = ((uint64_t)(l - 1) << 40) + ((uint64_t)(int64_t)dl << 20);
                 dz *= kGamma;
@@ -264,7 +266,7 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
                 Y.s = sw;
                 push(lc, X);
                 if (l < K) {
-                    exchange(xch, slot, nt, lane, wl, wr, Y);
+                    exchange<odd>(xch, slot, nt, lane, wl, wr, Y);
                     X = Y;
                 } else if (active) {
                     const uint32_t boff = (base_off + (uint32_t)(dl * (int)wd)) * 8u;  // 0 <= dl < T
@@ -341,7 +343,7 @@ hipError_t launch_batch_t(BatchHeader* hdr, MemberDesc* members, const GroupDesc
                           const WaveDesc* waves, uint32_t* done, uint32_t grid, uint32_t nt,
                           hipStream_t st) {
     hipLaunchKernelGGL((k_batch<K, FORCE, MASK, RULES>), dim3(grid), dim3(nt),
-                       (2 * nt + 1) * sizeof(uint32_t), st, hdr, members, groups, waves, done);
+                       2 * nt * sizeof(uint4) + sizeof(uint32_t), st, hdr, members, groups, waves, done);
     return hipGetLastError();
 }
 
@@ -594,7 +596,7 @@ int engine_grid(uint32_t K, bool force, bool mask, uint32_t rules, uint32_t nt, 
     FHP_HIP_TRY(hipGetDevice(&dev), "device");
     FHP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "attr");
     FHP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)nt,
-                                                            (2 * nt + 1) * sizeof(uint32_t)),
+                                                            2 * nt * sizeof(uint4) + sizeof(uint32_t)),
                 "occupancy");
     *grid = (uint32_t)((per_cu < 1 ? 1 : per_cu) * cus);
     return FHP_OK;

@@ -16,10 +16,13 @@
 //
 // Horizontal carries.  A 1-node shift of a word needs one bit of the
 // neighbouring word: bit 63 of the left word for rotl1, bit 0 of the right
-// word for rotr1.  After a row is produced each thread publishes those bits of
-// the six moving planes in one LDS dword, the workgroup synchronises, and
-// each thread reads its two neighbours' dwords (wrapping at the row ends).
-// Two LDS slots alternate so that one barrier per exchange suffices.
+// word for rotr1.  After a row is produced each thread publishes, in one
+// 16-byte LDS entry, the four 32-bit halves of its word that its neighbours
+// will shift in over the row's life (which four depends on the row's parity),
+// the workgroup synchronises, and each thread reads its two neighbours'
+// entries (wrapping at the row ends).  Every shift is then two funnel shifts
+// (v_alignbit) with no bit packing.  Two LDS slots alternate so that one
+// barrier per exchange suffices.
 //
 // Row parity.  Odd rows are shifted by +1/2, so which planes shift depends on
 // the parity of the destination row.  With y0 and H even it equals the
@@ -50,7 +53,7 @@ template <int K, bool FORCE, bool MASK, int RULES>
 __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
                                                 uint64_t* __restrict__ out,
                                                 const uint64_t* __restrict__ S, StepkArgs a) {
-    extern __shared__ uint32_t xch[];  // 2 slots x blockDim.x dwords
+    extern __shared__ uint4 xch[];  // 2 slots x blockDim.x entries
     const uint32_t nt = blockDim.x;
     const uint32_t lane = threadIdx.x;
     const bool valid = lane < a.wd;
@@ -87,20 +90,22 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
     };
     uint32_t slot = 0;
 
-    // Level l keeps two rows of level l-1: rho-1 (only planes 3, 4 and its carry
-    // bits are read again) and rho (everything).  Flat arrays indexed by
+    // Level l keeps two rows of level l-1: rho-1 (only planes 3, 4 and one
+    // neighbour half are read again) and rho (everything).  Flat arrays indexed by
     // compile-time levels stay in registers.
     uint64_t a3[K + 1], a4[K + 1], bp[K + 1][7], bs[K + 1];
-    uint32_t ac[K + 1], bc[K + 1];
+    uint32_t ac[K + 1], b2[K + 1], b5[K + 1], bq[K + 1];
     auto push = [&](auto lc, const Row& x) __attribute__((always_inline)) {
         constexpr int l = decltype(lc)::value;
         a3[l] = bp[l][3];
         a4[l] = bp[l][4];
-        ac[l] = bc[l];
+        ac[l] = bq[l];
 #pragma unroll
         for (int c = 0; c < 7; c++) bp[l][c] = x.p[c];
         bs[l] = x.s;
-        bc[l] = x.c;
+        b2[l] = x.c[1];
+        b5[l] = x.c[2];
+        bq[l] = x.c[3];
     };
     Row nxt;
     load(wrap_row((int)y0 - K), nxt);
@@ -117,7 +122,7 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
         uint64_t s = MASK ? X.s : 0ull;
         if (a.walls && (y == 0 || y == H - 1)) s = ~0ull;
         X.s = s;
-        exchange(xch, slot, nt, lane, wl, wr, X);
+        exchange<((PAR + K) & 1) != 0>(xch, slot, nt, lane, wl, wr, X);  // y0 even: parity of y
         bool have = true;  // X holds a new row of level l-1
         static_for<1, K>([&](auto lc) __attribute__((always_inline)) {
             constexpr int l = decltype(lc)::value;
@@ -132,7 +137,7 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
             const uint32_t rho = wrap_row(r - l);
             constexpr bool odd = ((PAR + K + l) & 1) != 0;  // parity of rho
             uint64_t n[7];
-            stream_in<odd>(a3[l], a4[l], ac[l], bp[l], bc[l], X, n);
+            stream_in<odd>(a3[l], a4[l], ac[l], bp[l], b2[l], b5[l], X, n);
             const uint64_t sw = bs[l];
             const uint64_t R = row_term(a.t0 + (uint64_t)(l - 1), rho);
             const uint64_t chi = (mix64(base_chi + R) & a.chi_and) | a.chi_or;
@@ -142,7 +147,7 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
             Y.s = sw;
             push(lc, X);
             if (l < K) {
-                exchange(xch, slot, nt, lane, wl, wr, Y);
+                exchange<odd>(xch, slot, nt, lane, wl, wr, Y);
                 X = Y;
             } else if (valid) {
                 const uint32_t off = offset(rho);
@@ -173,7 +178,7 @@ hipError_t launch_k(const uint64_t* in, uint64_t* out, const Lattice& L, const S
     const uint32_t nt = (L.wd + 63) / 64 * 64;
     const uint32_t bands = (L.H + a.T - 1) / a.T;
     hipLaunchKernelGGL((k_stepk<K, FORCE, MASK, RULES>), dim3(bands), dim3(nt),
-                       2 * nt * sizeof(uint32_t), st, in, out, L.S, a);
+                       2 * nt * sizeof(uint4), st, in, out, L.S, a);
     return hipGetLastError();
 }
 

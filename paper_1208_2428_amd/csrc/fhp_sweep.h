@@ -17,17 +17,37 @@
 
 namespace fhp {
 
-// One row of one level, as seen by one thread (one 64-node word).
+// One row of one level, as seen by one thread (one 64-node word).  A 1-node
+// shift of a word needs one bit of a neighbouring word: bit 63 of the left
+// word for rotl1 (its high half, whose bit 31 is that bit), bit 0 of the right
+// word for rotr1 (its low half).  Over its life a row of parity P is rotated
+// in four planes:
+//   as the row below its destination (dest y = row - 1): plane 0 (rotr1) if
+//       the row is even, plane 1 (rotl1) if odd;
+//   as the destination row: planes 2 (rotl1) and 5 (rotr1);
+//   as the row above (dest y = row + 1): plane 4 (rotr1) if even, plane 3
+//       (rotl1) if odd.
+// c[0..3] hold the neighbour halves for these four uses, in this order.
 struct Row {
     uint64_t p[7];  // planes
     uint64_t s;     // solid word (obstacles + wall rows)
-    uint32_t c;     // carry-in bits: bit 0..2 = bit 63 of the left word's planes 1, 2, 3;
-                    // bit 8..10 = bit 0 of the right word's planes 0, 4, 5
+    uint32_t c[4];  // neighbour halves: as row below, planes 2 and 5, as row above
 };
 
-__device__ __forceinline__ uint64_t rotl1(uint64_t v, uint32_t cin) { return (v << 1) | cin; }
-__device__ __forceinline__ uint64_t rotr1(uint64_t v, uint32_t cin) {
-    return (v >> 1) | ((uint64_t)cin << 63);
+__device__ __forceinline__ uint32_t lo32(uint64_t v) { return (uint32_t)v; }
+__device__ __forceinline__ uint32_t hi32(uint64_t v) { return (uint32_t)(v >> 32); }
+
+// v shifted one node towards larger x; left_hi = high half of the left word.
+__device__ __forceinline__ uint64_t rotl1(uint64_t v, uint32_t left_hi) {
+    const uint32_t lo = __builtin_amdgcn_alignbit(lo32(v), left_hi, 31);
+    const uint32_t hi = __builtin_amdgcn_alignbit(hi32(v), lo32(v), 31);
+    return ((uint64_t)hi << 32) | lo;
+}
+// v shifted one node towards smaller x; right_lo = low half of the right word.
+__device__ __forceinline__ uint64_t rotr1(uint64_t v, uint32_t right_lo) {
+    const uint32_t lo = __builtin_amdgcn_alignbit(hi32(v), lo32(v), 1);
+    const uint32_t hi = __builtin_amdgcn_alignbit(right_lo, hi32(v), 1);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 // Calls f(integral_constant<int, I>) for I = L .. N.
@@ -45,44 +65,51 @@ __device__ __forceinline__ void lds_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
-// The bits a row's word gives to its neighbours: bit 63 of planes 1, 2, 3
-// (sources of rotl1 for the word on its right) and bit 0 of planes 0, 4, 5
-// (sources of rotr1 for the word on its left).
-__device__ __forceinline__ uint32_t carry_out(const Row& x) {
-    return (uint32_t)(x.p[1] >> 63) | ((uint32_t)(x.p[2] >> 63) << 1) |
-           ((uint32_t)(x.p[3] >> 63) << 2) | ((uint32_t)(x.p[0] & 1) << 8) |
-           ((uint32_t)(x.p[4] & 1) << 9) | ((uint32_t)(x.p[5] & 1) << 10);
-}
-
-// Publishes x's carry bits in LDS slot `slot`, synchronises the workgroup and
-// gathers the carry-in bits from the words at lanes wl (left) and wr (right).
-__device__ __forceinline__ void exchange(uint32_t* xch, uint32_t& slot, uint32_t nt,
-                                         uint32_t lane, uint32_t wl, uint32_t wr, Row& x) {
-    uint32_t* buf = xch + slot * nt;
-    buf[lane] = carry_out(x);
+// Publishes the halves of x that the neighbouring words will need (for a row
+// of parity ODD) in LDS slot `slot` (nt entries of 16 bytes), synchronises the
+// workgroup and gathers x's neighbour halves from the words at lanes wl (left)
+// and wr (right).
+template <bool ODD>
+__device__ __forceinline__ void exchange(uint4* xch, uint32_t& slot, uint32_t nt, uint32_t lane,
+                                         uint32_t wl, uint32_t wr, Row& x) {
+    uint4* buf = xch + slot * nt;
+    uint4 mine;
+    if (ODD) mine = make_uint4(hi32(x.p[1]), hi32(x.p[2]), lo32(x.p[5]), hi32(x.p[3]));
+    else mine = make_uint4(lo32(x.p[0]), hi32(x.p[2]), lo32(x.p[5]), lo32(x.p[4]));
+    buf[lane] = mine;
     lds_barrier();
-    x.c = (buf[wl] & 0x7u) | (buf[wr] & 0x700u);
+    const uint4 l = buf[wl], r = buf[wr];
+    if (ODD) {
+        x.c[0] = l.x;
+        x.c[3] = l.w;
+    } else {
+        x.c[0] = r.x;
+        x.c[3] = r.w;
+    }
+    x.c[1] = l.y;
+    x.c[2] = r.z;
     slot ^= 1;
 }
 
 // Pull streaming of one destination row of parity ODD from the level below:
-// rows rho-1 (planes 3, 4 and carries ac), rho (bp, carries bc) and rho+1 (x).
+// rows y-1 (planes 3, 4 and its neighbour half as the row above, ac), y (bp,
+// neighbour halves of planes 2 and 5, b2 and b5) and y+1 (x).
 template <bool ODD>
 __device__ __forceinline__ void stream_in(uint64_t a3, uint64_t a4, uint32_t ac, const uint64_t* bp,
-                                          uint32_t bc, const Row& x, uint64_t n[7]) {
-    if (ODD) {
+                                          uint32_t b2, uint32_t b5, const Row& x, uint64_t n[7]) {
+    if (ODD) {  // row y-1 even, row y+1 even
         n[3] = a3;
-        n[4] = rotr1(a4, (ac >> 9) & 1);
-        n[0] = rotr1(x.p[0], (x.c >> 8) & 1);
+        n[4] = rotr1(a4, ac);
+        n[0] = rotr1(x.p[0], x.c[0]);
         n[1] = x.p[1];
-    } else {
-        n[3] = rotl1(a3, (ac >> 2) & 1);
+    } else {  // row y-1 odd, row y+1 odd
+        n[3] = rotl1(a3, ac);
         n[4] = a4;
         n[0] = x.p[0];
-        n[1] = rotl1(x.p[1], x.c & 1);
+        n[1] = rotl1(x.p[1], x.c[0]);
     }
-    n[2] = rotl1(bp[2], (bc >> 1) & 1);
-    n[5] = rotr1(bp[5], (bc >> 10) & 1);
+    n[2] = rotl1(bp[2], b2);
+    n[5] = rotr1(bp[5], b5);
     n[6] = bp[6];
 }
 
