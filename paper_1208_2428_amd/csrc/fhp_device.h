@@ -188,15 +188,17 @@ FHP_HD void collide_fhp3(const uint32_t a[7], uint32_t s, uint32_t chi, uint32_t
 
 // Update of 32 nodes after streaming: collision (fluid) or bounce-back
 // (solid) of rule set RULES, then forcing: bits 5 -> 2 where the coin is up,
-// on fluid nodes with o5 set and o2 clear.  coin has at most one bit.
+// on fluid nodes with o5 set and o2 clear.  coin has at most one bit; up is
+// all ones (the coin counts) or zero (it does not).
 template <int RULES = kRulesFHP2>
-FHP_HD void update32(const uint32_t a[7], uint32_t s, uint32_t chi, uint32_t coin, uint32_t o[7]) {
+FHP_HD void update32(const uint32_t a[7], uint32_t s, uint32_t chi, uint32_t coin, uint32_t up,
+                     uint32_t o[7]) {
     if constexpr (RULES == kRulesFHP3) {
         collide_fhp3(a, s, chi, o);
     } else {
         collide_fhp12<RULES>(a, counts(a), s, chi, o);
     }
-    const uint32_t cf = coin & ~s;
+    const uint32_t cf = lop3<kA & ~kB & kC>(coin, s, up);
     const uint32_t o5 = lop3<kA & ~(kB & ~kC)>(o[5], cf, o[2]);
     const uint32_t o2 = lop3<kA | (kB & kC)>(o[2], cf, o[5]);
     o[5] = o5;
@@ -205,14 +207,14 @@ FHP_HD void update32(const uint32_t a[7], uint32_t s, uint32_t chi, uint32_t coi
 
 // 64-node version: the two 32-bit halves independently.
 template <int RULES = kRulesFHP2>
-FHP_HD void update(const uint64_t a[7], uint64_t solid, uint64_t chi, uint64_t coin,
+FHP_HD void update(const uint64_t a[7], uint64_t solid, uint64_t chi, uint64_t coin, uint32_t up,
                    uint64_t o[7]) {
     uint32_t lo[7], hi[7], olo[7], ohi[7];
     for (int c = 0; c < 7; c++) {
         lo[c] = (uint32_t)a[c];
         hi[c] = (uint32_t)(a[c] >> 32);
     }
-    update32<RULES>(lo, (uint32_t)solid, (uint32_t)chi, (uint32_t)coin, olo);
+    update32<RULES>(lo, (uint32_t)solid, (uint32_t)chi, (uint32_t)coin, up, olo);
 #if defined(__HIP_DEVICE_COMPILE__)
     // The halves are independent; interleaving them buys no speed on a
     // wave-serial SIMD but nearly doubles the live values (FHP-II at depth 4:
@@ -221,14 +223,33 @@ FHP_HD void update(const uint64_t a[7], uint64_t solid, uint64_t chi, uint64_t c
 #pragma unroll
     for (int c = 0; c < 7; c++) asm volatile("" : "+v"(hi[c]) : "v"(olo[c]));
 #endif
-    update32<RULES>(hi, (uint32_t)(solid >> 32), (uint32_t)(chi >> 32), (uint32_t)(coin >> 32), ohi);
+    update32<RULES>(hi, (uint32_t)(solid >> 32), (uint32_t)(chi >> 32), (uint32_t)(coin >> 32), up,
+                    ohi);
     for (int c = 0; c < 7; c++) o[c] = ((uint64_t)ohi[c] << 32) | olo[c];
 }
 
-// Forcing coin word: h = H(key_force, counter); the coin of node h>>58 is up
-// when (h mod 2^32) < thr, thr = floor(f * 2^38) < 2^32.
-FHP_HD uint64_t coin_word(uint64_t h, uint64_t thr) {
-    return ((h & 0xffffffffull) < thr) ? (1ull << (h >> 58)) : 0ull;
+// The same with a coin word that is up wherever it has a bit.
+template <int RULES = kRulesFHP2>
+FHP_HD void update(const uint64_t a[7], uint64_t solid, uint64_t chi, uint64_t coin, uint64_t o[7]) {
+    update<RULES>(a, solid, chi, coin, ~0u, o);
+}
+
+// Forcing coin of one 64-node word, h = H(key_force, counter): the coin of
+// node h>>58 is up when (h mod 2^32) < thr, thr = floor(f * 2^38) < 2^32.
+// The blocked kernels keep it as that node's bit (coin_bit) and a mask that
+// is all ones when the coin is up (coin_up); the forcing step folds the mask
+// into a bit function it evaluates anyway.
+FHP_HD uint64_t coin_bit(uint64_t h) { return 1ull << (h >> 58); }
+FHP_HD uint32_t coin_up(uint64_t h, uint64_t thr) { return ((uint32_t)h < (uint32_t)thr) ? ~0u : 0u; }
+FHP_HD uint64_t coin_word(uint64_t h, uint64_t thr) { return coin_up(h, thr) ? coin_bit(h) : 0ull; }
+
+// Chirality word of a chirality mode: (h & m_and) | m_or on each 32-bit half
+// (m_and, m_or are all ones or all zeros).  With m_and in a vector register
+// each half is one three-input bit function.
+FHP_HD uint64_t chir_word(uint64_t h, uint32_t m_and, uint32_t m_or) {
+    const uint32_t lo = lop3<(kA & kB) | kC>((uint32_t)h, m_and, m_or);
+    const uint32_t hi = lop3<(kA & kB) | kC>((uint32_t)(h >> 32), m_and, m_or);
+    return ((uint64_t)hi << 32) | lo;
 }
 
 }  // namespace fhp

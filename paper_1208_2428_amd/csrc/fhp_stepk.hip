@@ -1,209 +1,9 @@
-// fhp_stepk.hip -- temporally blocked FHP update: K time steps per pass over
-// HBM (K = 1..FHP_MAX_DEPTH).
-//
-// Decomposition.  A workgroup owns a band of T consecutive rows (T even) and
-// the full lattice width: thread w holds 64-node word w of every row it
-// touches, so the periodic wrap in x needs no halo words.  The band sweeps
-// downwards through rows y0-K .. y0+T+K-1 of the input buffer, one row per
-// iteration.  Level 0 is the loaded row; level l (1..K) is the state after l
-// steps, and its row rho = r - l is computed as soon as level l-1 has
-// produced rows rho-1, rho and rho+1 (pull streaming reads exactly those).
-// Each level keeps the last two rows of the level below it in registers, so
-// every input row is read from HBM once per band and only the 2K halo rows
-// are read twice (by the neighbouring bands).  Level K rows y0 .. y0+T-1 are
-// stored.  The first 2K iterations fill the pipeline; after that every
-// iteration produces one row of every level.
-//
-// Horizontal carries.  A 1-node shift of a word needs one bit of the
-// neighbouring word: bit 63 of the left word for rotl1, bit 0 of the right
-// word for rotr1.  After a row is produced each thread publishes, in one
-// 16-byte LDS entry, the four 32-bit halves of its word that its neighbours
-// will shift in over the row's life (which four depends on the row's parity),
-// the workgroup synchronises, and each thread reads its two neighbours'
-// entries (wrapping at the row ends).  Every shift is then two funnel shifts
-// (v_alignbit) with no bit packing.  Two LDS slots alternate so that one
-// barrier per exchange suffices.
-//
-// Row parity.  Odd rows are shifted by +1/2, so which planes shift depends on
-// the parity of the destination row.  With y0 and H even it equals the
-// parity of (i + K + l) for iteration i and level l; the sweep is unrolled by
-// two so that parity is a compile-time constant in every level.
-//
-// Time: level l of a pass starting at t0 applies step t0 + l - 1 (hash
-// counters use that t and the absolute row index, so results do not depend
-// on K or on the band height).
-#include "fhp_device.h"
-#include "fhp_internal.h"
-#include "fhp_sweep.h"
+// fhp_stepk.hip -- the temporally blocked pass (kernel in fhp_stepk.h) for
+// state buffers below 4 GiB, and the dispatch by depth, rule set and buffer
+// size.
+#include "fhp_stepk.h"
 
 namespace fhp {
-namespace {
-
-struct StepkArgs {
-    uint32_t H, wd;        // rows, words per row
-    uint32_t T;            // band height (even)
-    uint32_t walls;        // rows 0 and H-1 solid
-    uint64_t ps;           // plane stride in words
-    uint64_t t0;           // steps done before this pass
-    uint64_t key_chir, key_force, thr_force;
-    uint64_t chi_and, chi_or;  // chirality word = (hash & chi_and) | chi_or
-};
-
-template <int K, bool FORCE, bool MASK, int RULES>
-__global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
-                                                uint64_t* __restrict__ out,
-                                                const uint64_t* __restrict__ S, StepkArgs a) {
-    extern __shared__ uint4 xch[];  // 2 slots x blockDim.x entries
-    const uint32_t nt = blockDim.x;
-    const uint32_t lane = threadIdx.x;
-    const bool valid = lane < a.wd;
-    const uint32_t w = valid ? lane : 0;
-    const uint32_t wl = w ? w - 1 : a.wd - 1;
-    const uint32_t wr = (w + 1 == a.wd) ? 0 : w + 1;
-    const uint32_t H = a.H;
-    // Bands in launch order: workgroups go round-robin over the 8 XCDs, so
-    // neighbouring bands run on different XCDs at the same time.  Giving each
-    // XCD a contiguous run of bands instead measured 8% slower at K = 4 and
-    // 19% slower at K = 2 on the 16384^2 lattice.
-    const uint32_t y0 = blockIdx.x * a.T;
-    const uint32_t rows = min(a.T, H - y0);
-    const int n_iter = (int)rows + 2 * K;
-    const uint64_t base_chi = word_base(a.key_chir, w);
-    const uint64_t base_frc = word_base(a.key_force, w);
-
-    auto wrap_row = [&](int r) __attribute__((always_inline)) -> uint32_t {
-        int m = r % (int)H;
-        return (uint32_t)(m < 0 ? m + (int)H : m);
-    };
-    // Byte offset of word w of row y within a plane (planes are < 4 GiB).
-    auto offset = [&](uint32_t y) __attribute__((always_inline)) -> uint32_t { return (y * a.wd + w) * 8u; };
-    auto plane_in = [&](int c, uint32_t off) __attribute__((always_inline)) -> uint64_t {
-        return *(const uint64_t*)((const char*)(in + c * a.ps) + off);
-    };
-    // Issues the loads of row y; wall rows are applied when the row is
-    // consumed, so that nothing waits on these loads before the next row.
-    auto load = [&](uint32_t y, Row& x) __attribute__((always_inline)) {
-        const uint32_t off = offset(y);
-#pragma unroll
-        for (int c = 0; c < 7; c++) x.p[c] = plane_in(c, off);
-        if (MASK) x.s = *(const uint64_t*)((const char*)S + off);
-    };
-    uint32_t slot = 0;
-
-    // Level l keeps two rows of level l-1: rho-1 (only planes 3, 4 and one
-    // neighbour half are read again) and rho (everything).  Flat arrays indexed by
-    // compile-time levels stay in registers.
-    uint64_t a3[K + 1], a4[K + 1], bp[K + 1][7], bs[K + 1];
-    uint32_t ac[K + 1], b2[K + 1], b5[K + 1], bq[K + 1];
-    auto push = [&](auto lc, const Row& x) __attribute__((always_inline)) {
-        constexpr int l = decltype(lc)::value;
-        a3[l] = bp[l][3];
-        a4[l] = bp[l][4];
-        ac[l] = bq[l];
-#pragma unroll
-        for (int c = 0; c < 7; c++) bp[l][c] = x.p[c];
-        bs[l] = x.s;
-        b2[l] = x.c[1];
-        b5[l] = x.c[2];
-        bq[l] = x.c[3];
-    };
-    Row nxt;
-    load(wrap_row((int)y0 - K), nxt);
-
-    // One sweep iteration.  FULL: every level is active (i >= 2K).  PAR: i & 1.
-    auto body = [&](int i, auto full_c, auto par_c) __attribute__((always_inline)) {
-        constexpr bool FULL = decltype(full_c)::value;
-        constexpr int PAR = decltype(par_c)::value;
-        const int r = (int)y0 - K + i;
-        const uint32_t y = wrap_row(r);
-        Row X = nxt;
-        // prefetch the next row (the last iteration reloads its own row)
-        load((i + 1 < n_iter) ? wrap_row(r + 1) : y, nxt);
-        uint64_t s = MASK ? X.s : 0ull;
-        if (a.walls && (y == 0 || y == H - 1)) s = ~0ull;
-        X.s = s;
-        exchange<((PAR + K) & 1) != 0>(xch, slot, nt, lane, wl, wr, X);  // y0 even: parity of y
-        bool have = true;  // X holds a new row of level l-1
-        static_for<1, K>([&](auto lc) __attribute__((always_inline)) {
-            constexpr int l = decltype(lc)::value;
-            if (!FULL) {
-                if (!have) return;
-                if (i < 2 * l) {
-                    push(lc, X);
-                    have = false;
-                    return;
-                }
-            }
-            const uint32_t rho = wrap_row(r - l);
-            constexpr bool odd = ((PAR + K + l) & 1) != 0;  // parity of rho
-            uint64_t n[7];
-            stream_in<odd>(a3[l], a4[l], ac[l], bp[l], b2[l], b5[l], X, n);
-            const uint64_t sw = bs[l];
-            const uint64_t R = row_term(a.t0 + (uint64_t)(l - 1), rho);
-            const uint64_t chi = (mix64(base_chi + R) & a.chi_and) | a.chi_or;
-            const uint64_t coin = FORCE ? coin_word(mix64(base_frc + R), a.thr_force) : 0ull;
-            Row Y;
-            update<RULES>(n, sw, chi, coin, Y.p);
-            Y.s = sw;
-            push(lc, X);
-            if (l < K) {
-                exchange<odd>(xch, slot, nt, lane, wl, wr, Y);
-                X = Y;
-            } else if (valid) {
-                const uint32_t off = offset(rho);
-#pragma unroll
-                for (int c = 0; c < 7; c++) *(uint64_t*)((char*)(out + c * a.ps) + off) = Y.p[c];
-            }
-        });
-    };
-
-    using F = std::false_type;
-    using T = std::true_type;
-    using P0 = std::integral_constant<int, 0>;
-    using P1 = std::integral_constant<int, 1>;
-    int i = 0;
-    for (; i < 2 * K; i += 2) {  // pipeline fill (n_iter >= 2K + 2)
-        body(i, F{}, P0{});
-        body(i + 1, F{}, P1{});
-    }
-    for (; i < n_iter; i += 2) {  // rows is even, so n_iter - 2K is even
-        body(i, T{}, P0{});
-        body(i + 1, T{}, P1{});
-    }
-}
-
-template <int K, bool FORCE, bool MASK, int RULES = kRulesFHP2>
-hipError_t launch_k(const uint64_t* in, uint64_t* out, const Lattice& L, const StepkArgs& a,
-                    hipStream_t st) {
-    const uint32_t nt = (L.wd + 63) / 64 * 64;
-    const uint32_t bands = (L.H + a.T - 1) / a.T;
-    hipLaunchKernelGGL((k_stepk<K, FORCE, MASK, RULES>), dim3(bands), dim3(nt),
-                       2 * nt * sizeof(uint4), st, in, out, L.S, a);
-    return hipGetLastError();
-}
-
-// FHP-II has a kernel for every combination of forcing and obstacles; the
-// other rule sets use the forcing variant (a zero rate draws no coin).
-template <int K>
-hipError_t launch_k2(const uint64_t* in, uint64_t* out, const Lattice& L, const StepkArgs& a,
-                     uint32_t rules, hipStream_t st) {
-    const bool force = a.thr_force != 0, mask = L.S != nullptr;
-    if (rules == kRulesFHP1)
-        return mask ? launch_k<K, true, true, kRulesFHP1>(in, out, L, a, st)
-                    : launch_k<K, true, false, kRulesFHP1>(in, out, L, a, st);
-    if (rules == kRulesFHP3) {
-        if constexpr (K <= kMaxDepthFHP3)
-            return mask ? launch_k<K, true, true, kRulesFHP3>(in, out, L, a, st)
-                        : launch_k<K, true, false, kRulesFHP3>(in, out, L, a, st);
-        return hipErrorInvalidValue;
-    }
-    if (force) return mask ? launch_k<K, true, true>(in, out, L, a, st)
-                           : launch_k<K, true, false>(in, out, L, a, st);
-    return mask ? launch_k<K, false, true>(in, out, L, a, st)
-                : launch_k<K, false, false>(in, out, L, a, st);
-}
-
-}  // namespace
 
 hipError_t launch_stepk(uint32_t K, const uint64_t* in, uint64_t* out, const Lattice& L,
                         const Dyn& D, uint64_t t, uint32_t T, hipStream_t st) {
@@ -217,16 +17,10 @@ hipError_t launch_stepk(uint32_t K, const uint64_t* in, uint64_t* out, const Lat
     a.key_chir = D.key_chir;
     a.key_force = D.key_force;
     a.thr_force = D.thr_force;
-    a.chi_and = (D.chir_mode == FHP_CHIR_HASH) ? ~0ull : 0ull;
-    a.chi_or = (D.chir_mode == FHP_CHIR_ONE) ? ~0ull : 0ull;
-    switch (K) {
-        case 1: return launch_k2<1>(in, out, L, a, D.rules, st);
-        case 2: return launch_k2<2>(in, out, L, a, D.rules, st);
-        case 3: return launch_k2<3>(in, out, L, a, D.rules, st);
-        case 4: return launch_k2<4>(in, out, L, a, D.rules, st);
-        case 5: return launch_k2<5>(in, out, L, a, D.rules, st);
-        default: return hipErrorInvalidValue;
-    }
+    a.chi_and = (D.chir_mode == FHP_CHIR_HASH) ? ~0u : 0u;
+    a.chi_or = (D.chir_mode == FHP_CHIR_ONE) ? ~0u : 0u;
+    if (planes_wide(L.ps)) return launch_stepk_wide(K, in, out, L, a, D.rules, st);
+    return launch_depth<false>(K, in, out, L, a, D.rules, st);
 }
 
 }  // namespace fhp

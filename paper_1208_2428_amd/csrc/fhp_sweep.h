@@ -59,6 +59,74 @@ __device__ __forceinline__ void static_for(F&& f) {
     }
 }
 
+// Pins a wave-uniform 64-bit value in scalar registers.  Left alone, the
+// compiler folds the row term's multiply into a vector multiply-add with the
+// per-word hash base (two vector instructions per hash instead of one add).
+__device__ __forceinline__ uint64_t in_sgprs(uint64_t v) {
+    asm("" : "+s"(v));
+    return v;
+}
+
+// A region of num_bytes bytes at p as a buffer resource (gfx9 layout, 32-bit
+// data format).  Accesses take a 32-bit byte offset in a vector register and
+// one in a scalar register; the hardware returns zero for loads and drops
+// stores beyond num_bytes.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t region_rsrc(const void* p, uint32_t num_bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, (int)num_bytes, 0x00020000);
+}
+__device__ __forceinline__ uint64_t buf_load64(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, (int)soff, 0);
+    return ((uint64_t)v[1] << 32) | v[0];
+}
+__device__ __forceinline__ void buf_store64(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff,
+                                            uint64_t x) {
+    __attribute__((ext_vector_type(2))) uint32_t v;
+    v[0] = (uint32_t)x;
+    v[1] = (uint32_t)(x >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, (int)soff, 0);
+}
+
+// The seven planes of one state buffer (plane stride ps words, planes of
+// plane_bytes bytes), accessed by plane and by the byte offset of a word
+// within its plane.  An access is then a buffer resource in scalar registers
+// plus that 32-bit offset; with plain pointers the compiler forms a 64-bit
+// vector address per plane and row.  WIDE = false: the whole buffer is below
+// 4 GiB, one resource, and the plane is a scalar offset.  WIDE = true: one
+// resource per plane (every plane is below 4 GiB).
+template <bool WIDE>
+struct Planes;
+
+template <>
+struct Planes<false> {
+    __amdgpu_buffer_rsrc_t r;
+    uint32_t ps8;
+    __device__ __forceinline__ Planes(const uint64_t* base, uint64_t ps, uint32_t) {
+        r = region_rsrc(base, (uint32_t)(7 * ps * 8));
+        ps8 = (uint32_t)(ps * 8);
+    }
+    __device__ __forceinline__ uint64_t load(int c, uint32_t off) const { return buf_load64(r, off, c * ps8); }
+    __device__ __forceinline__ void store(int c, uint32_t off, uint64_t x) const {
+        buf_store64(r, off, c * ps8, x);
+    }
+};
+
+template <>
+struct Planes<true> {
+    __amdgpu_buffer_rsrc_t r[7];
+    __device__ __forceinline__ Planes(const uint64_t* base, uint64_t ps, uint32_t plane_bytes) {
+#pragma unroll
+        for (int c = 0; c < 7; c++) r[c] = region_rsrc(base + c * ps, plane_bytes);
+    }
+    __device__ __forceinline__ uint64_t load(int c, uint32_t off) const { return buf_load64(r[c], off, 0); }
+    __device__ __forceinline__ void store(int c, uint32_t off, uint64_t x) const {
+        buf_store64(r[c], off, 0, x);
+    }
+};
+
+// True when a buffer of seven planes of stride ps words needs a resource per
+// plane.
+inline bool planes_wide(uint64_t ps) { return 7 * ps * 8 > 0xffffffffull; }
+
 // Workgroup barrier that orders LDS traffic only: global loads issued for the
 // next row stay in flight across it.
 __device__ __forceinline__ void lds_barrier() {

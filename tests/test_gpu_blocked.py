@@ -83,3 +83,27 @@ def test_fixed_points_blocked():
         s.set_state(np.full((20, 256), v, np.uint8), 0)
         s.step(9)
         assert np.all(s.get_state() == v)
+
+
+def test_state_buffer_above_4gib():
+    """A state buffer whose seven planes span more than 4 GiB is addressed with
+    one buffer resource per plane instead of one per buffer.  Its blocked
+    passes (depths 5 and 2) must equal single steps, which use plain 64-bit
+    pointers, on the same 32768 x 149798 channel (7 x 613 MB per buffer)."""
+    import torch
+    W, H = 32768, 149798
+    assert 7 * (H * W // 64) * 8 > 2 ** 32
+    got = {}
+    for K in (1, 5):
+        say("wide buffer", W, H, "depth", K)
+        s = Sim(W, H, seed=9, fill=0.3, force_rate=1e-3, walls=True, depth=K)
+        m0 = s.observe_global()["mass"]
+        s.step(5)
+        s.step(7)  # at depth 5: passes of 5 and 2 steps
+        g = s.observe_global()
+        got[K] = (s.digest(), int(g["mass"]), int(g["px"]), int(g["py"]))
+        assert got[K][1] == m0
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+    assert got[5] == got[1]
