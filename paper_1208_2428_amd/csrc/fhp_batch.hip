@@ -39,6 +39,10 @@
 namespace fhp {
 namespace {
 
+// Pointers into global memory (address space 1).
+using GlobalU64 = __attribute__((address_space(1))) uint64_t;
+using GlobalChar = __attribute__((address_space(1))) char;
+
 struct MemberDesc {
     uint64_t* buf[2];
     const uint64_t* S;   // obstacle plane or nullptr
@@ -163,15 +167,17 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
         const uint32_t wl = valid ? first + (w ? w - 1 : wd - 1) : lane;
         const uint32_t wr = valid ? first + ((w + 1 == wd) ? 0 : w + 1) : lane;
         const uint32_t cur = (uni(M->cur) + p) & 1;
-        const uint64_t* in = (const uint64_t*)uni((uint64_t)M->buf[cur]);
-        uint64_t* out = (uint64_t*)uni((uint64_t)M->buf[cur ^ 1]);
-        const uint64_t* S = MASK ? (const uint64_t*)uni((uint64_t)M->S) : nullptr;
+        // global (not generic) pointers: generic accesses would also count
+        // against the LDS wait of every carry exchange
+        const GlobalU64* in = (const GlobalU64*)uni((uint64_t)M->buf[cur]);
+        GlobalU64* out = (GlobalU64*)uni((uint64_t)M->buf[cur ^ 1]);
+        const GlobalU64* S = MASK ? (const GlobalU64*)uni((uint64_t)M->S) : nullptr;
         const uint64_t ps = uni(M->ps);
         const bool walls = uni(M->walls) != 0;
         const uint64_t tp = uni(M->t0) + (uint64_t)p * K;
-        const uint32_t chi_and32 = uni(M->chi_and), chi_or32 = uni(M->chi_or);
-        const uint64_t chi_and = ((uint64_t)chi_and32 << 32) | chi_and32;
-        const uint64_t chi_or = ((uint64_t)chi_or32 << 32) | chi_or32;
+        uint32_t chi_and = uni(M->chi_and);  // kept in a vector register (see chir_word)
+        asm("" : "+v"(chi_and));
+        const uint32_t chi_or = uni(M->chi_or);
         const uint64_t thr = uni(M->thr_force);
         const bool top = b == 0, bot = b + 1 == nb;  // bands whose halos wrap
         const uint32_t y0 = b * T;
@@ -195,8 +201,8 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
         auto load = [&](int d, Row& x) __attribute__((always_inline)) {
             const uint32_t boff = row_off(d) * 8u;
 #pragma unroll
-            for (int c = 0; c < 7; c++) x.p[c] = *(const uint64_t*)((const char*)(in + c * ps) + boff);
-            if (MASK) x.s = S ? *(const uint64_t*)((const char*)S + boff) : 0ull;
+            for (int c = 0; c < 7; c++) x.p[c] = *(const GlobalU64*)((const GlobalChar*)(in + c * ps) + boff);
+            if (MASK) x.s = S ? *(const GlobalU64*)((const GlobalChar*)S + boff) : 0ull;
         };
 
         uint64_t a3[K + 1], a4[K + 1], bp[K + 1][7], bs[K + 1];
@@ -248,7 +254,7 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
                 stream_in<odd>(a3[l], a4[l], ac[l], bp[l], b2[l], b5[l], X, n);
                 const uint64_t sw = bs[l];
                 uint64_t dz = ((uint64_t)(l - 1) << 40) + ((uint64_t)(int64_t)dl << 20);
-                dz *= kGamma;
+                dz = in_sgprs(dz * kGamma);
                 uint64_t zc = zc0 + dz, zf = zf0 + dz;
                 if (dl < 0) {
                     const uint64_t fix = top ? HG : 0ull;
@@ -259,10 +265,10 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
                     zc -= fix;
                     zf -= fix;
                 }
-                const uint64_t chi = (mix64(zc) & chi_and) | chi_or;
-                const uint64_t coin = FORCE ? coin_word(mix64(zf), thr) : 0ull;
+                const uint64_t chi = chir_word(mix64(zc), chi_and, chi_or);
+                const uint64_t hf = FORCE ? mix64(zf) : 0ull;
                 Row Y;
-                update<RULES>(n, sw, chi, coin, Y.p);
+                update<RULES>(n, sw, chi, FORCE ? coin_bit(hf) : 0ull, FORCE ? coin_up(hf, thr) : 0u, Y.p);
                 Y.s = sw;
                 push(lc, X);
                 if (l < K) {
@@ -271,7 +277,7 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
                 } else if (active) {
                     const uint32_t boff = (base_off + (uint32_t)(dl * (int)wd)) * 8u;  // 0 <= dl < T
 #pragma unroll
-                    for (int c = 0; c < 7; c++) *(uint64_t*)((char*)(out + c * ps) + boff) = Y.p[c];
+                    for (int c = 0; c < 7; c++) *(GlobalU64*)((GlobalChar*)(out + c * ps) + boff) = Y.p[c];
                 }
             });
         };

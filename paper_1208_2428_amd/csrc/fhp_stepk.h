@@ -171,6 +171,17 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
         body(i, F{}, P0{});
         body(i + 1, F{}, P1{});
     }
+    // Steady state, six rows per trip: a row's planes 3 and 4 stay live for
+    // three iterations, and with two iterations per trip the compiler
+    // rotates them through registers with moves (about 6 per word and level).
+    for (; i + 6 <= n_iter; i += 6) {
+        body(i, T{}, P0{});
+        body(i + 1, T{}, P1{});
+        body(i + 2, T{}, P0{});
+        body(i + 3, T{}, P1{});
+        body(i + 4, T{}, P0{});
+        body(i + 5, T{}, P1{});
+    }
     for (; i < n_iter; i += 2) {  // rows is even, so n_iter - 2K is even
         body(i, T{}, P0{});
         body(i + 1, T{}, P1{});
