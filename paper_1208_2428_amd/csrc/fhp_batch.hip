@@ -88,11 +88,11 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
                                                const GroupDesc* __restrict__ groups,
                                                const WaveDesc* __restrict__ waves,
                                                uint32_t* __restrict__ done) {
-    extern __shared__ uint4 xch[];  // 2 carry slots x nt entries, then one broadcast word
+    extern __shared__ uint32_t xch[];  // 2 carry slots x 4 halves x nt entries, then one broadcast word
     const uint32_t nt = blockDim.x;
     const uint32_t lane = threadIdx.x;
     const uint32_t wave = uni(lane >> 6);
-    uint32_t* bcast = reinterpret_cast<uint32_t*>(xch + 2 * nt);
+    uint32_t* bcast = xch + 8 * nt;
     const uint32_t n_groups = hdr->n_groups;
     const uint32_t passes = hdr->passes;
     const uint32_t n_items = n_groups * passes;

@@ -16,13 +16,13 @@
 //
 // Horizontal carries.  A 1-node shift of a word needs one bit of the
 // neighbouring word: bit 63 of the left word for rotl1, bit 0 of the right
-// word for rotr1.  After a row is produced each thread publishes, in one
-// 16-byte LDS entry, the four 32-bit halves of its word that its neighbours
-// will shift in over the row's life (which four depends on the row's parity),
-// the workgroup synchronises, and each thread reads its two neighbours'
-// entries (wrapping at the row ends).  Every shift is then two funnel shifts
-// (v_alignbit) with no bit packing.  Two LDS slots alternate so that one
-// barrier per exchange suffices.
+// word for rotr1.  After a row is produced each thread publishes in LDS the
+// four 32-bit halves of its word that its neighbours will shift in over the
+// row's life (which four depends on the row's parity), the workgroup
+// synchronises, and each thread reads its two neighbours' halves (wrapping at
+// the row ends).  Every shift is then two funnel shifts (v_alignbit) with no
+// bit packing.  Two LDS slots alternate so that one barrier per exchange
+// suffices.
 //
 // Row parity.  Odd rows are shifted by +1/2, so which planes shift depends on
 // the parity of the destination row.  With y0 and H even it equals the
@@ -52,12 +52,13 @@ struct StepkArgs {
 
 namespace {
 
+constexpr size_t kStepkLdsBytes = 2 * 4 * kMaxBlockedWords * sizeof(uint32_t);
+
 template <int K, bool FORCE, bool MASK, int RULES, bool WIDE>
 __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
                                                 uint64_t* __restrict__ out,
                                                 const uint64_t* __restrict__ S, StepkArgs a) {
-    extern __shared__ uint4 xch[];  // 2 slots x blockDim.x entries
-    const uint32_t nt = blockDim.x;
+    extern __shared__ uint32_t xch[];  // 2 slots x 4 halves x kMaxBlockedWords entries
     const uint32_t lane = threadIdx.x;
     const bool valid = lane < a.wd;
     const uint32_t w = valid ? lane : 0;
@@ -126,7 +127,23 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
         load((i + 1 < n_iter) ? wrap_row(r + 1) : y, nxt);
         const uint64_t wall = (a.walls && (y == 0 || y == H - 1)) ? ~0ull : 0ull;  // uniform
         X.s = MASK ? (X.s | wall) : wall;
-        exchange<((PAR + K) & 1) != 0>(xch, slot, nt, lane, wl, wr, X);  // y0 even: parity of y
+        // The hash words of the next level do not depend on the exchange, so
+        // they are formed between publishing a row and the barrier.
+        uint64_t chi = 0, coin = 0;
+        uint32_t up = 0;
+        auto hashes = [&](int l) __attribute__((always_inline)) {
+            const uint64_t R = in_sgprs(row_term(a.t0 + (uint64_t)(l - 1), wrap_row(r - l)));
+            chi = chir_word(mix64(base_chi + R), chi_and, a.chi_or);
+            if (FORCE) {
+                const uint64_t hf = mix64(base_frc + R);
+                coin = coin_bit(hf);
+                up = coin_up(hf, a.thr_force);
+            }
+        };
+        constexpr bool odd0 = ((PAR + K) & 1) != 0;  // y0 even: parity of y
+        publish<odd0>(xch, slot, kMaxBlockedWords, lane, X);
+        if (FULL || i >= 2) hashes(1);
+        gather<odd0>(xch, slot, kMaxBlockedWords, wl, wr, X);
         bool have = true;  // X holds a new row of level l-1
         static_for<1, K>([&](auto lc) __attribute__((always_inline)) {
             constexpr int l = decltype(lc)::value;
@@ -143,16 +160,14 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
             uint64_t n[7];
             stream_in<odd>(a3[l], a4[l], ac[l], bp[l], b2[l], b5[l], X, n);
             const uint64_t sw = bs[l];
-            const uint64_t R = in_sgprs(row_term(a.t0 + (uint64_t)(l - 1), rho));
-            const uint64_t chi = chir_word(mix64(base_chi + R), chi_and, a.chi_or);
-            const uint64_t hf = FORCE ? mix64(base_frc + R) : 0ull;
             Row Y;
-            update<RULES>(n, sw, chi, FORCE ? coin_bit(hf) : 0ull, FORCE ? coin_up(hf, a.thr_force) : 0u,
-                          Y.p);
+            update<RULES>(n, sw, chi, coin, up, Y.p);
             Y.s = sw;
             push(lc, X);
             if (l < K) {
-                exchange<odd>(xch, slot, nt, lane, wl, wr, Y);
+                publish<odd>(xch, slot, kMaxBlockedWords, lane, Y);
+                if (FULL || i >= 2 * (l + 1)) hashes(l + 1);
+                gather<odd>(xch, slot, kMaxBlockedWords, wl, wr, Y);
                 X = Y;
             } else if (valid) {
                 const uint32_t off = offset(rho);
@@ -193,7 +208,7 @@ hipError_t launch_k(const uint64_t* in, uint64_t* out, const Lattice& L, const S
                     hipStream_t st) {
     const uint32_t nt = (L.wd + 63) / 64 * 64;
     const uint32_t bands = (L.H + a.T - 1) / a.T;
-    hipLaunchKernelGGL((k_stepk<K, FORCE, MASK, RULES, WIDE>), dim3(bands), dim3(nt), 2 * nt * sizeof(uint4),
+    hipLaunchKernelGGL((k_stepk<K, FORCE, MASK, RULES, WIDE>), dim3(bands), dim3(nt), kStepkLdsBytes,
                        st, in, out, L.S, a);
     return hipGetLastError();
 }

@@ -133,30 +133,45 @@ __device__ __forceinline__ void lds_barrier() {
     asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
+// The carry exchange lives in LDS as two slots of four 32-bit arrays (one per
+// published half) of `stride` entries each: a lane's four halves are 4-byte
+// words `stride` apart, so that lanes reading consecutive neighbours hit
+// consecutive banks (16-byte entries per lane made every read a 4-way bank
+// conflict).
+
 // Publishes the halves of x that the neighbouring words will need (for a row
-// of parity ODD) in LDS slot `slot` (nt entries of 16 bytes), synchronises the
-// workgroup and gathers x's neighbour halves from the words at lanes wl (left)
-// and wr (right).
+// of parity ODD) in LDS slot `slot`.
 template <bool ODD>
-__device__ __forceinline__ void exchange(uint4* xch, uint32_t& slot, uint32_t nt, uint32_t lane,
-                                         uint32_t wl, uint32_t wr, Row& x) {
-    uint4* buf = xch + slot * nt;
-    uint4 mine;
-    if (ODD) mine = make_uint4(hi32(x.p[1]), hi32(x.p[2]), lo32(x.p[5]), hi32(x.p[3]));
-    else mine = make_uint4(lo32(x.p[0]), hi32(x.p[2]), lo32(x.p[5]), lo32(x.p[4]));
-    buf[lane] = mine;
+__device__ __forceinline__ void publish(uint32_t* xch, uint32_t slot, uint32_t stride, uint32_t lane,
+                                        const Row& x) {
+    uint32_t* buf = xch + slot * 4 * stride + lane;
+    buf[0] = ODD ? hi32(x.p[1]) : lo32(x.p[0]);
+    buf[stride] = hi32(x.p[2]);
+    buf[2 * stride] = lo32(x.p[5]);
+    buf[3 * stride] = ODD ? hi32(x.p[3]) : lo32(x.p[4]);
+}
+
+// Synchronises the workgroup and gathers x's neighbour halves from what the
+// words at lanes wl (left) and wr (right) published; the next exchange uses
+// the other slot.
+template <bool ODD>
+__device__ __forceinline__ void gather(const uint32_t* xch, uint32_t& slot, uint32_t stride, uint32_t wl,
+                                       uint32_t wr, Row& x) {
+    const uint32_t* buf = xch + slot * 4 * stride;
     lds_barrier();
-    const uint4 l = buf[wl], r = buf[wr];
-    if (ODD) {
-        x.c[0] = l.x;
-        x.c[3] = l.w;
-    } else {
-        x.c[0] = r.x;
-        x.c[3] = r.w;
-    }
-    x.c[1] = l.y;
-    x.c[2] = r.z;
+    const uint32_t n = ODD ? wl : wr;  // the side planes 0/1 and 3/4 shift in from
+    x.c[0] = buf[n];
+    x.c[1] = buf[stride + wl];
+    x.c[2] = buf[2 * stride + wr];
+    x.c[3] = buf[3 * stride + n];
     slot ^= 1;
+}
+
+template <bool ODD>
+__device__ __forceinline__ void exchange(uint32_t* xch, uint32_t& slot, uint32_t stride, uint32_t lane,
+                                         uint32_t wl, uint32_t wr, Row& x) {
+    publish<ODD>(xch, slot, stride, lane, x);
+    gather<ODD>(xch, slot, stride, wl, wr, x);
 }
 
 // Pull streaming of one destination row of parity ODD from the level below:
