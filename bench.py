@@ -318,7 +318,7 @@ def main() -> int:
     }
     if valu is not None:
         # the same launch against the VALU issue limit (wave64 instructions;
-        # quarter-rate multiplies, 7% of them, count once here)
+        # integer multiplies issue at the bit-operation rate on this GPU)
         rate = valu / launch_s
         out["alu"] = {"bound": "alu", "achieved": rate, "peak": VALU_WAVE_INSTR_PEAK,
                       "unit": "wave64 VALU instructions/s", "frac": rate / VALU_WAVE_INSTR_PEAK,
