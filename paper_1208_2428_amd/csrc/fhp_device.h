@@ -105,39 +105,39 @@ FHP_HD Counts counts(const uint32_t a[7]) {
 // Z = rest for R3.  The rule that applies comes from the number of moving
 // particles: R1 = (n = 2) & (an opposite pair present); R3 = rest ? (n = 1) :
 // ((n = 2) & both particles in one class, i.e. at 120 deg); R2 = (n = 3),
-// channels 0, 2, 4 equal (and no rest for FHP-II).
+// channels 0, 2, 4 equal (and no rest for FHP-II).  The rule masks ignore
+// the solid bit: a solid node takes the bounced channel j+3 in the last
+// select whatever its rule mask says, and keeps its rest bit.
 template <int RULES>
 FHP_HD void collide_fhp12(const uint32_t a[7], const Counts& K, uint32_t s, uint32_t chi,
                           uint32_t o[7]) {
     const uint32_t r = a[6];
-    const uint32_t is1 = lop3<kA & ~kB & ~kC>(K.n0, K.n1, K.n2);
     const uint32_t is2 = lop3<~kA & kB & ~kC>(K.n0, K.n1, K.n2);
     const uint32_t is3 = K.n0 & K.n1;  // n = 7 cannot occur
     uint32_t c12, c3, zc;
     if constexpr (RULES == kRulesFHP1) {
         const uint32_t tri = is3 & K.eq024;                                   // R2
-        c12 = lop3<((kA & kB) | kC) & 0xFF>(is2, K.pp, tri) & ~s;             // R1 or R2, fluid
+        c12 = lop3<((kA & kB) | kC) & 0xFF>(is2, K.pp, tri);                  // R1 or R2
         c3 = 0;
         zc = ~chi;
     } else {
         const uint32_t tri = lop3<kA & kB & ~kC>(is3, K.eq024, r);          // R2
-        c12 = lop3<((kA & kB) | kC) & 0xFF>(is2, K.pp, tri) & ~s;             // R1 or R2, fluid
-        const uint32_t f3 = lop3<kA & ~kB & ~kC>(is2, K.se, s);             // two at 120 deg, fluid
-        const uint32_t e3 = lop3<kA & kB & ~kC>(r, is1, s);                 // one + rest, fluid
-        c3 = lop3<(kA & kB) | (~kA & kC)>(r, e3, f3);                       // R3, fluid
+        c12 = lop3<((kA & kB) | kC) & 0xFF>(is2, K.pp, tri);                  // R1 or R2
+        const uint32_t is1 = lop3<kA & ~kB & ~kC>(K.n0, K.n1, K.n2);
+        const uint32_t f3 = is2 & ~K.se;                                      // two at 120 deg
+        c3 = lop3<(kA & kB) | (~kA & kC)>(r, is1, f3);                      // R3: r ? n = 1 : f3
         zc = lop3<(kA & ~kB) | (~kA & kC)>(c12, chi, r);                    // c12 ? ~chi : r
     }
     const uint32_t any = c12 | c3;                                          // a rule applies
-    const uint32_t keep = lop3<~(kA | kB)>(any, s, 0);                      // unchanged node
 #pragma unroll
     for (int j = 0; j < 6; j++) {
         const uint32_t am = a[(j + 5) % 6], ap = a[(j + 1) % 6];
         const uint32_t z = lop3<kA ^ (kB & kC)>(zc, c12, am);             // zc ^ (c12 & A)
         const uint32_t sp = lop3<(((kA ^ kB) & kC) | (~(kA ^ kB) & kA)) & 0xFF>(am, ap, z);
-        const uint32_t alt = mux3(any, sp, a[(j + 3) % 6]);                // collide or bounce
-        o[j] = mux3(keep, a[j], alt);
+        const uint32_t fl = mux3(any, sp, a[j]);                           // fluid: collide or keep
+        o[j] = mux3(s, a[(j + 3) % 6], fl);                                // solid: bounce back
     }
-    o[6] = r ^ c3;
+    o[6] = lop3<kA ^ (kB & ~kC)>(r, c3, s);                               // r ^ (c3 & ~s)
 }
 
 // Collision-saturated FHP-III.  Nodes of mass >= 4 are handled through their
