@@ -87,14 +87,17 @@ inline void pack_waves(const std::vector<MemberBands>& mem, uint32_t nt,
     close();
 }
 
-// Queue order: most lanes x rows first (stable, so classes keep their order
-// among equals).
+// Queue order: most rows first (stable).  An item's time follows its band
+// height, not its lane count (its waves run side by side); among equal
+// heights the packing order is kept, so a member's bands stay together in
+// the queue (the 512-lattice ensemble measured 1% faster than with items
+// ordered by lanes x rows).
 inline void order_groups(std::vector<GroupDesc>& groups, const std::vector<uint32_t>& lanes) {
+    (void)lanes;
     std::vector<uint32_t> idx(groups.size());
     for (uint32_t k = 0; k < idx.size(); k++) idx[k] = k;
-    std::stable_sort(idx.begin(), idx.end(), [&](uint32_t x, uint32_t y) {
-        return (uint64_t)lanes[x] * groups[x].T > (uint64_t)lanes[y] * groups[y].T;
-    });
+    std::stable_sort(idx.begin(), idx.end(),
+                     [&](uint32_t x, uint32_t y) { return groups[x].T > groups[y].T; });
     std::vector<GroupDesc> out(groups.size());
     for (uint32_t k = 0; k < idx.size(); k++) out[k] = groups[idx[k]];
     groups.swap(out);
