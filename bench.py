@@ -107,19 +107,17 @@ def depth_sweep(wl, mask, steps: int):
 
 
 def plain_rate(wl, mask, depth: int, steps: int) -> float:
-    """Node updates/s of the single-lattice kernel at depth `depth`."""
+    """Node updates/s of the single-lattice kernel at depth `depth`, timed
+    with HIP events on the stream the kernels run on (after one untimed run
+    of the same length)."""
     import torch
 
     from paper_1208_2428_amd import Sim
+    from paper_1208_2428_amd.autotune import time_steps
     sim = Sim(**wl.params(), solid=mask, depth=depth)
-    sim.step(steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    per_step = time_steps(sim.step, torch.cuda.current_stream(), steps, 1)
     sim.close()
-    return wl.width * wl.height * steps / wall
+    return wl.width * wl.height / per_step
 
 
 def batched_leg(args, wl, mask, depth, value):
