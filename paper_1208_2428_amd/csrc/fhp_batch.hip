@@ -357,12 +357,16 @@ __global__ void k_batch_header(BatchHeader* hdr, uint32_t passes, uint32_t K) {
     hdr->K = K;
 }
 
+// Dynamic LDS of the batch kernel: two exchange slots of four 32-bit arrays
+// of nt entries, then one broadcast word.
+constexpr size_t batch_lds_bytes(uint32_t nt) { return 2 * 4 * (size_t)nt * sizeof(uint32_t) + sizeof(uint32_t); }
+
 template <int K, bool FORCE, bool MASK, int RULES>
 hipError_t launch_batch_t(BatchHeader* hdr, MemberDesc* members, const GroupDesc* groups,
                           const WaveDesc* waves, uint32_t* done, uint32_t grid, uint32_t nt,
                           hipStream_t st) {
-    hipLaunchKernelGGL((k_batch<K, FORCE, MASK, RULES>), dim3(grid), dim3(nt),
-                       2 * nt * sizeof(uint4) + sizeof(uint32_t), st, hdr, members, groups, waves, done);
+    hipLaunchKernelGGL((k_batch<K, FORCE, MASK, RULES>), dim3(grid), dim3(nt), batch_lds_bytes(nt), st, hdr,
+                       members, groups, waves, done);
     return hipGetLastError();
 }
 
@@ -614,8 +618,7 @@ int engine_grid(uint32_t K, bool force, bool mask, uint32_t rules, uint32_t nt, 
     int per_cu = 0, dev = 0, cus = 0;
     FHP_HIP_TRY(hipGetDevice(&dev), "device");
     FHP_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "attr");
-    FHP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)nt,
-                                                            2 * nt * sizeof(uint4) + sizeof(uint32_t)),
+    FHP_HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, (int)nt, batch_lds_bytes(nt)),
                 "occupancy");
     *grid = (uint32_t)((per_cu < 1 ? 1 : per_cu) * cus);
     return FHP_OK;

@@ -20,7 +20,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 # Sources of the blocked single-lattice kernel: the traffic recorded under
 # profiles/ applies only while they are unchanged.
-KERNEL_SOURCES = ["csrc/fhp_stepk.hip", "csrc/fhp_sweep.h", "csrc/fhp_device.h"]
+KERNEL_SOURCES = ["csrc/fhp_stepk.h", "csrc/fhp_stepk.hip", "csrc/fhp_sweep.h", "csrc/fhp_device.h"]
 
 
 def kernel_source_hash() -> str:
