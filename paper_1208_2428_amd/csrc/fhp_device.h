@@ -67,21 +67,23 @@ FHP_HD uint32_t or3(uint32_t a, uint32_t b, uint32_t c) { return lop3<kA | kB | 
 constexpr int kRulesFHP2 = 0, kRulesFHP1 = 1, kRulesFHP3 = 2;
 
 // Particle counts of the six moving channels of 32 nodes, by parity class:
-// n = n0 + 2 n1 + 4 n2; se = parity of the even-class count; pp = a head-on
-// pair is present; eq024 = channels 0, 2, 4 all equal.
+// even class (0, 2, 4) count = 2 ce + se, odd class (1, 3, 5) = 2 co + so;
+// total n = n0 + 2 n1 + 4 n2; pp = a head-on pair is present; eq024 =
+// channels 0, 2, 4 all equal.
 struct Counts {
-    uint32_t se, n0, n1, n2, pp, eq024;
+    uint32_t se, ce, so, co, n0, n1, n2, pp, eq024;
 };
 
 FHP_HD Counts counts(const uint32_t a[7]) {
     Counts K;
     K.se = xor3(a[0], a[2], a[4]);
-    const uint32_t ce = maj3(a[0], a[2], a[4]);
-    const uint32_t so = xor3(a[1], a[3], a[5]), co = maj3(a[1], a[3], a[5]);
-    K.n0 = K.se ^ so;
-    const uint32_t c0 = K.se & so;
-    K.n1 = xor3(ce, co, c0);
-    K.n2 = maj3(ce, co, c0);
+    K.ce = maj3(a[0], a[2], a[4]);
+    K.so = xor3(a[1], a[3], a[5]);
+    K.co = maj3(a[1], a[3], a[5]);
+    K.n0 = K.se ^ K.so;
+    const uint32_t c0 = K.se & K.so;
+    K.n1 = xor3(K.ce, K.co, c0);
+    K.n2 = maj3(K.ce, K.co, c0);
     uint32_t pp = a[0] & a[3];
     pp = lop3<kA | (kB & kC)>(pp, a[1], a[4]);
     K.pp = lop3<kA | (kB & kC)>(pp, a[2], a[5]);
@@ -153,7 +155,22 @@ FHP_HD void collide_fhp3(const uint32_t a[7], uint32_t s, uint32_t chi, uint32_t
     uint32_t b[7];
 #pragma unroll
     for (int c = 0; c < 7; c++) b[c] = a[c] ^ cm;
-    const Counts K = counts(b);
+    // Counts of the complemented state from those of a: a class of three
+    // channels with e particles has 3 - e after the complement, which flips
+    // both bits of e (so the parity of the total is unchanged).
+    Counts K;
+    K.se = K0.se ^ cm;
+    K.ce = K0.ce ^ cm;
+    K.so = K0.so ^ cm;
+    K.co = K0.co ^ cm;
+    K.n0 = K0.n0;
+    const uint32_t c0 = K.se & K.so;
+    K.n1 = xor3(K.ce, K.co, c0);
+    K.n2 = maj3(K.ce, K.co, c0);
+    // head-on pairs (k, k+3) one by one: the three-cycles need them singly
+    const uint32_t P0 = b[0] & b[3], P1 = b[1] & b[4], P2 = b[2] & b[5];
+    K.pp = or3(P0, P1, P2);
+    K.eq024 = lop3<(kA & kB & kC) | (~kA & ~kB & ~kC)>(b[0], b[2], b[4]);
     uint32_t ob[7];
     collide_fhp12<kRulesFHP2>(b, K, s, chi, ob);
     const uint32_t rb = b[6];
@@ -162,25 +179,38 @@ FHP_HD void collide_fhp3(const uint32_t a[7], uint32_t s, uint32_t chi, uint32_t
     // three moving with a head-on pair, no rest; two at 120 deg plus rest
     const uint32_t p3 = lop3<kA & ~kB & ~kC>(is3 & K.pp, rb, s);
     const uint32_t p2 = lop3<kA & ~kB & kC>(is2, K.se, rb) & ~s;
-    // results of the cycles, accumulated per channel (few live values: the
-    // blocked kernel keeps its rows in registers)
+    // A_j holds the pair (j+1, j+4) and B_j the pair (j+2, j+5), each with
+    // particle j: q[k] marks the p3 nodes whose pair is (k, k+3)
+    const uint32_t q[3] = {p3 & P0, p3 & P1, p3 & P2};
+    // Results of the cycles, gathered per channel: channel c collects A_c,
+    // A_{c-1}, A_{c+2}, B_c, B_{c-2}, B_{c+1}, C_{c-1}, C_{c+1}; the rest bit
+    // every C.  A_j and B_{j+2} both add to channel j+4, so each A_j waits two
+    // steps for its partner; the C_j pair up for the rest bit.
     uint32_t nw[7] = {0, 0, 0, 0, 0, 0, 0};
+    uint32_t tA_hold[6] = {0, 0, 0, 0, 0, 0};
+    uint32_t tC_prev = 0;
 #pragma unroll
     for (int j = 0; j < 6; j++) {
-        const int j1 = (j + 1) % 6, j2 = (j + 2) % 6, j4 = (j + 4) % 6, j5 = (j + 5) % 6;
-        const uint32_t iA = lop3<kA & kB & kC>(p3, b[j], b[j1]) & b[j4];
-        const uint32_t iB = lop3<kA & kB & kC>(p3, b[j], b[j2]) & b[j5];
+        const int j1 = (j + 1) % 6, j2 = (j + 2) % 6, j5 = (j + 5) % 6;
+        const uint32_t iA = q[(j + 1) % 3] & b[j];
+        const uint32_t iB = q[(j + 2) % 3] & b[j];
         const uint32_t iC = lop3<kA & kB & kC>(p2, b[j1], b[j5]);
         const uint32_t tA = mux3(chi, iC, iB);  // nodes whose result is A_j = {j, j+1, j+4}
         const uint32_t tB = mux3(chi, iA, iC);  // B_j = {j, j+2, j+5}
         const uint32_t tC = mux3(chi, iB, iA);  // C_j = {j+1, j+5} + rest
         nw[j] = or3(nw[j], tA, tB);
         nw[j1] = or3(nw[j1], tA, tC);
-        nw[j4] |= tA;
-        nw[j2] |= tB;
         nw[j5] = or3(nw[j5], tB, tC);
-        nw[6] |= tC;
+        tA_hold[j] = tA;
+        // channel j+2 = (j-2)+4: A_{j-2} with B_j (A_{j-2} of j < 2 waits for the wrap)
+        if (j >= 2) nw[j2] = or3(nw[j2], tA_hold[j - 2], tB);
+        else nw[j2] |= tB;
+        if (j & 1) nw[6] = or3(nw[6], tC_prev, tC);
+        else tC_prev = tC;
     }
+    // A_4 and A_5 add to channels 2 and 3
+    nw[2] |= tA_hold[4];
+    nw[3] |= tA_hold[5];
     const uint32_t cyc = p3 | p2;
 #pragma unroll
     for (int k = 0; k < 7; k++) o[k] = lop3<(kA & ~kB) | kC>(ob[k], cyc, nw[k]) ^ cm;
