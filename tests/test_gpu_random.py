@@ -1,14 +1,14 @@
-"""Randomised GPU vs oracle parity of the single-lattice step: 160 seeded
-configurations drawn over widths, heights, depths, band heights, walls,
-obstacles (solid nodes holding particles included), forcing rates,
-chirality modes, rule sets and step sequences, each compared bit for bit
-with the oracle after every call.  The draws are fixed by the seed, so a
-failure names a reproducible case."""
+"""Randomised GPU vs oracle parity: 160 seeded single-lattice configurations
+drawn over widths, heights, depths, band heights, walls, obstacles (solid
+nodes holding particles included), forcing rates, chirality modes, rule sets
+and step sequences; 24 seeded batches with random tilings; 12 seeded job
+streams through pools.  Every result is compared bit for bit with the oracle.
+The draws are fixed by the seeds, so a failure names a reproducible case."""
 import numpy as np
 import pytest
 
 import oracle
-from paper_1208_2428_amd import Batch, Sim
+from paper_1208_2428_amd import Batch, Pool, Sim
 from paper_1208_2428_amd import workloads as WL
 
 pytestmark = pytest.mark.gpu
@@ -107,3 +107,39 @@ def test_random_batch(case):
                                           err_msg=f"batch case {case} member {i} at t={t + n}")
         t += n
     b.close()
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_random_pool(case):
+    """Seeded job streams through a pool: jobs of random size, step count and
+    physics (one rule set per pool) admitted between ticks of random length,
+    each finished job's state compared with the oracle."""
+    rng = np.random.default_rng(9000 + case)
+    rules = [oracle.RULES_FHP2, oracle.RULES_FHP1, oracle.RULES_FHP3][case % 3]
+    depth = int(rng.integers(1, RULE_DEPTH[rules] + 1))
+    pool = Pool(Pool.arena_bytes_for(16, 4096, 32 << 20), max_slots=16, max_bands=4096,
+                depth=depth, rules=rules, group_threads=int(rng.choice([0, 64, 256])))
+    jobs = []
+    for _ in range(int(rng.integers(4, 10))):
+        jobs.append((dict(width=int(64 * rng.integers(1, 8)), height=int(2 * rng.integers(4, 48)),
+                          seed=int(rng.integers(0, 2 ** 40)), fill=float(rng.uniform(0.05, 0.6)),
+                          walls=bool(rng.random() < 0.5),
+                          force_rate=float(rng.choice([0.0, 1e-3, 1.0 / 80])), rules=rules),
+                     int(rng.integers(0, 30))))
+    print("random pool", case, depth, [(p["width"], p["height"], n) for p, n in jobs], flush=True)
+    slot_of, got, pending = {}, {}, list(range(len(jobs)))
+    while pending or len(got) < len(jobs):
+        for _ in range(int(rng.integers(0, 3))):  # admit a few, then tick a few passes
+            if pending:
+                k = pending.pop(0)
+                s = pool.admit(jobs[k][1], **jobs[k][0])
+                assert s is not None
+                slot_of[s] = k
+        pool.tick(int(rng.integers(1, 4)))
+        for s in pool.done():
+            got[slot_of[s]] = pool.member(s).get_state()
+            pool.release(s)
+    for k, (p, n) in enumerate(jobs):
+        ref = oracle.init(p["width"], p["height"], p["seed"], p["fill"], walls=p["walls"])
+        ref, _ = oracle.run(ref, 0, n, p["seed"], p["force_rate"], threads=THREADS, rules=rules)
+        np.testing.assert_array_equal(got[k], ref, err_msg=f"pool case {case} job {k}")
