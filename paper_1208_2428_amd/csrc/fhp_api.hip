@@ -94,10 +94,11 @@ Layout layout_for(uint32_t W, uint32_t H) {
 
 // Default temporal-block depth where the blocked kernel applies (full-row
 // workgroups, at most kMaxBlockedWords words per row): the deepest whose
-// register queue fits without spilling.  On the 16384^2 porous lattice the
-// pass is then bound by VALU work rather than by HBM traffic; depth 5 moves
-// 18% fewer HBM bytes per step than depth 4 for 3% more halo work and
-// measured 3-4% faster.
+// register queue fits without spilling.  On the 16384^2 porous lattice every
+// shallower depth runs at the copy bandwidth of HBM (halo rows included);
+// depth 5 moves 18% fewer bytes per step than depth 4 for 3% more halo work,
+// measured 3-6% faster, and is near both that bandwidth and the VALU issue
+// limit.
 uint32_t default_depth(uint32_t wd) { return wd <= kMaxBlockedWords ? FHP_MAX_DEPTH : 1; }
 
 // Default band height of the blocked kernel: 32 rows balances the halo rows
@@ -277,18 +278,25 @@ int fhp_observe(fhp_sim* s, int kind, uint32_t block, void* host_dst, size_t dst
     if (block == 0 || (block < 64 ? (64 % block) : (block % 64)))
         return fail(FHP_E_INVAL, "block %u must divide 64 or be a multiple of 64", block);
     const uint32_t bw = (L.W + block - 1) / block, bh = (L.H + block - 1) / block;
-    const size_t row_bytes = (size_t)bw * 3 * sizeof(int32_t);
+    const size_t blk_bytes = 3 * sizeof(int32_t), row_bytes = (size_t)bw * blk_bytes;
     if (dst_bytes < row_bytes * bh)
         return fail(FHP_E_NOMEM, "destination of %zu bytes, %zu needed", dst_bytes, row_bytes * bh);
     int32_t* stage = (int32_t*)s->buf[1 - s->cur];
-    uint32_t rows = (uint32_t)(staging_bytes(s) / row_bytes);
-    if (rows > bh) rows = bh;
-    for (uint32_t r0 = 0; r0 < bh; r0 += rows) {
-        const uint32_t n = (r0 + rows <= bh) ? rows : bh - r0;
-        FHP_HIP_TRY(launch_observe_blocks(planes, L, block, r0, n, stage, s->st), "blocks");
-        FHP_HIP_TRY(hipMemcpyAsync((char*)host_dst + (size_t)r0 * row_bytes, stage, n * row_bytes,
-                                   hipMemcpyDeviceToHost, s->st), "copy");
-        FHP_HIP_TRY(hipStreamSynchronize(s->st), "sync");
+    // The stage holds at least 7 planes of 32 words, i.e. 149 blocks: whole
+    // block rows when one fits, else pieces of one block row.
+    const size_t cap = staging_bytes(s) / blk_bytes;
+    const uint32_t rows = (uint32_t)((cap / bw < bh) ? cap / bw : bh);
+    const uint32_t cols = rows ? bw : (uint32_t)cap;
+    for (uint32_t r0 = 0; r0 < bh; r0 += rows ? rows : 1) {
+        const uint32_t n = rows ? ((r0 + rows <= bh) ? rows : bh - r0) : 1;
+        for (uint32_t c0 = 0; c0 < bw; c0 += cols) {
+            const uint32_t m = (c0 + cols <= bw) ? cols : bw - c0;
+            FHP_HIP_TRY(launch_observe_blocks(planes, L, block, r0, n, c0, m, stage, s->st), "blocks");
+            FHP_HIP_TRY(hipMemcpyAsync((char*)host_dst + ((size_t)r0 * bw + c0) * blk_bytes, stage,
+                                       (size_t)n * m * blk_bytes, hipMemcpyDeviceToHost, s->st),
+                        "copy");
+            FHP_HIP_TRY(hipStreamSynchronize(s->st), "sync");
+        }
     }
     return FHP_OK;
 }

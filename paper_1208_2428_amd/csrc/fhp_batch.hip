@@ -1172,7 +1172,8 @@ int fhp_pool_collect(fhp_pool* pl, uint32_t slot, uint32_t block, int32_t* host_
     if (!ps.collected) FHP_HIP_TRY(hipEventCreateWithFlags(&ps.collected, hipEventDisableTiming),
                                    "event");
     int32_t* stage = (int32_t*)s->buf[1 - s->cur];  // the idle buffer
-    FHP_HIP_TRY(launch_observe_blocks(s->buf[s->cur], lattice_of(s), block, 0, bh, stage, s->st),
+    FHP_HIP_TRY(launch_observe_blocks(s->buf[s->cur], lattice_of(s), block, 0, bh, 0, bw, stage,
+                                      s->st),
                 "blocks");
     FHP_HIP_TRY(hipMemcpyAsync(host_dst, stage, need, hipMemcpyDeviceToHost, s->st), "copy");
     FHP_HIP_TRY(hipEventRecord(ps.collected, s->st), "event");

@@ -72,7 +72,8 @@ hipError_t launch_observe_global(const uint64_t* planes, const Lattice& L, uint6
 hipError_t launch_observe_rows(const uint64_t* planes, const Lattice& L, uint32_t row0,
                                uint32_t rows, int64_t* out, hipStream_t st);
 hipError_t launch_observe_blocks(const uint64_t* planes, const Lattice& L, uint32_t b,
-                                 uint32_t brow0, uint32_t brows, int32_t* out, hipStream_t st);
+                                 uint32_t brow0, uint32_t brows, uint32_t bx0, uint32_t nbx,
+                                 int32_t* out, hipStream_t st);
 hipError_t launch_digest(const uint64_t* planes, const Lattice& L, uint64_t* acc, hipStream_t st);
 hipError_t launch_step1(const uint64_t* in, uint64_t* out, const Lattice& L, const Dyn& D,
                         uint64_t t, hipStream_t st);

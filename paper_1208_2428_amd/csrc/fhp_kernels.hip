@@ -132,16 +132,18 @@ __global__ void __launch_bounds__(kBlock) k_observe_global(const uint64_t* __res
     }
 }
 
-// Block sums over b x b node blocks: one thread per output block (by, bx).
-// b divides 64 (a block is a b-bit field of one word) or is a multiple of 64
-// (a block spans b/64 whole words).
+// Block sums over b x b node blocks: one thread per output block (by, bx),
+// for block rows brow0 .. brow0 + brows - 1 and block columns bx0 .. bx0 +
+// nbx - 1, written row-major (nbx blocks per row).  b divides 64 (a block is
+// a b-bit field of one word) or is a multiple of 64 (a block spans b/64
+// whole words).
 __global__ void __launch_bounds__(kBlock) k_observe_blocks(const uint64_t* __restrict__ planes,
                                                            Lattice L, uint32_t b, uint32_t brow0,
-                                                           uint32_t brows, int32_t* __restrict__ out) {
-    const uint32_t bw = (L.W + b - 1) / b;
+                                                           uint32_t brows, uint32_t bx0, uint32_t nbx,
+                                                           int32_t* __restrict__ out) {
     const size_t o = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    if (o >= (size_t)brows * bw) return;
-    const uint32_t by = brow0 + (uint32_t)(o / bw), bx = (uint32_t)(o % bw);
+    if (o >= (size_t)brows * nbx) return;
+    const uint32_t by = brow0 + (uint32_t)(o / nbx), bx = bx0 + (uint32_t)(o % nbx);
     const uint32_t y0 = by * b, y1 = min(L.H, y0 + b);
     int32_t rho = 0, px = 0, py = 0;
     uint32_t w0, w1;
@@ -317,11 +319,12 @@ hipError_t launch_observe_global(const uint64_t* planes, const Lattice& L, uint6
 }
 
 hipError_t launch_observe_blocks(const uint64_t* planes, const Lattice& L, uint32_t b,
-                                 uint32_t brow0, uint32_t brows, int32_t* out, hipStream_t st) {
-    const size_t n = (size_t)brows * ((L.W + b - 1) / b);
+                                 uint32_t brow0, uint32_t brows, uint32_t bx0, uint32_t nbx,
+                                 int32_t* out, hipStream_t st) {
+    const size_t n = (size_t)brows * nbx;
     if (!n) return hipSuccess;
     hipLaunchKernelGGL(k_observe_blocks, dim3(grid_for(n)), dim3(kBlock), 0, st, planes, L, b,
-                       brow0, brows, out);
+                       brow0, brows, bx0, nbx, out);
     return hipGetLastError();
 }
 

@@ -125,6 +125,21 @@ def test_observables_match_oracle():
     assert s.digest() == oracle.digest(st)
 
 
+@pytest.mark.parametrize("H", [2, 12])
+def test_block_sums_of_rows_wider_than_the_stage(H):
+    """Short, wide lattices: one row of 1- to 4-node blocks (12 bytes each)
+    holds more bytes than the idle buffer that stages host copies, so the
+    row goes over in pieces; 8-node blocks take whole rows."""
+    rng = np.random.default_rng(12)
+    W = 32768
+    st = WL.random_states(rng, H, W, p=0.4, solid_frac=0.1)
+    s = Sim(W, H, seed=1)
+    s.set_state(st, 0)
+    for b in (1, 2, 4, 8, 64):
+        say(f"block sums W={W} H={H} b={b}")
+        np.testing.assert_array_equal(s.observe_blocks(b), oracle.observe_blocks(st, b), err_msg=str(b))
+
+
 def test_channel_workload_first_steps():
     wl = WL.CHANNEL
     say("channel", wl)
