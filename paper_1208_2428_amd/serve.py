@@ -68,6 +68,10 @@ class Server:
                 idx, r = queue[0]
                 slot = pool.admit(r.steps, **job_params(r))
                 if slot is None:
+                    if not inflight:  # an empty pool has no room for it: it never will
+                        raise RuntimeError(
+                            f"request {idx} ({r.side} x {r.side}, {job_bytes(r.side)} bytes) "
+                            "does not fit the pool even when it is empty")
                     break
                 queue.popleft()
                 inflight[slot] = (idx, r)

@@ -97,6 +97,19 @@ def test_serving_loop_results_match_alone():
     srv.close()
 
 
+def test_serving_loop_rejects_a_job_larger_than_the_arena():
+    """A request that an empty pool cannot admit is an error, not a wait."""
+    srv = serve.Server(lattice_bytes=2 * serve.job_bytes(256), max_slots=4, max_bands=1024,
+                       group_threads=64)
+    ok = WL.Request(0.0, 256, 10, 1)
+    big = WL.Request(0.0, 1024, 10, 2)
+    out = srv.run([ok], realtime=False)
+    assert out["completed"] == 1
+    with pytest.raises(RuntimeError, match="does not fit"):
+        srv.run([ok, big], realtime=False)
+    srv.close()
+
+
 def test_asynchronous_collection_matches_result():
     pool = Pool(Pool.arena_bytes_for(4, 1024, 16 << 20), max_slots=4, max_bands=1024)
     p = dict(width=256, height=128, seed=21, fill=0.3, force_rate=1e-3, walls=True)
