@@ -66,7 +66,8 @@ def porous_mask(W: int, H: int, seed: int, rmin: int = 8, rmax: int = 32,
     `frac`.  Node (x, y) sits at (x + (y mod 2)/2, y*sqrt(3)/2), so in units of
     half a lattice constant 4*d^2 = dx^2 + 3*dy^2 with integer dx, dy: the
     whole construction is exact integer arithmetic.  A node is solid when its
-    distance to a centre is at most r.
+    distance to a centre is at most r.  Raises ValueError when 100,000 draws in
+    a row are rejected (the fraction lies beyond what such a packing reaches).
     """
     rng = np.random.default_rng(seed)
     solid = np.zeros((H, W), dtype=np.uint8)
@@ -76,6 +77,7 @@ def porous_mask(W: int, H: int, seed: int, rmin: int = 8, rmax: int = 32,
     cys = np.zeros(0, dtype=np.int64)
     crs = np.zeros(0, dtype=np.int64)
     rows = np.arange(-rmax, rmax + 1)
+    rejected = 0
     while count < target:
         x, y, r = (int(v) for v in (rng.integers(0, W), rng.integers(0, H),
                                     rng.integers(rmin, rmax + 1)))
@@ -84,7 +86,12 @@ def porous_mask(W: int, H: int, seed: int, rmin: int = 8, rmax: int = 32,
             dx = (xh - cxh + W) % (2 * W) - W
             dy = (y - cys + H // 2) % H - H // 2
             if np.any(dx * dx + 3 * dy * dy <= 4 * (r + crs) ** 2):
+                rejected += 1
+                if rejected == 100_000:
+                    raise ValueError(f"solid fraction {frac} not reached: {count} of {target} "
+                                     "nodes solid when the disks stopped fitting")
                 continue
+        rejected = 0
         cxh = np.append(cxh, xh)
         cys = np.append(cys, y)
         crs = np.append(crs, r)

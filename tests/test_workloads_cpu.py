@@ -17,6 +17,13 @@ def test_porous_mask_recipe():
     assert not np.array_equal(m, WL.porous_mask(W, H, seed=34))
 
 
+def test_porous_mask_beyond_packing_raises():
+    # radius-8 disks that may not overlap cannot cover 90% of a 64 x 64 box
+    import pytest
+    with pytest.raises(ValueError, match="not reached"):
+        WL.porous_mask(64, 64, seed=1, rmin=8, rmax=8, frac=0.9)
+
+
 def test_porous_disks_are_separated():
     # every solid node lies within r of exactly one accepted centre: recover
     # the disks by flood fill on the triangular lattice and check sizes
