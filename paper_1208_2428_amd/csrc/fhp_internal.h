@@ -55,7 +55,7 @@ int hip_fail(hipError_t e, const char* what);
 int validate(const fhp_params* p);
 Layout layout_for(uint32_t W, uint32_t H);
 uint32_t default_depth(uint32_t wd);
-uint32_t default_band(uint32_t H, uint32_t K);
+uint32_t default_band(uint32_t H, uint32_t wd, uint32_t simds);
 
 // Kernel launchers (fhp_kernels.hip).  All enqueue on `st` and return the HIP
 // launch status.
@@ -99,6 +99,7 @@ struct fhp_sim {
     uint64_t t;      // steps completed
     uint32_t depth;  // temporal-block depth K
     uint32_t band;   // rows per workgroup of the blocked kernel (0 = default)
+    uint32_t simds;  // SIMDs of the device the simulation runs on (4 per CU)
     int has_mask;
     hipStream_t st;
     void* owner;     // batch that owns this view, or nullptr
