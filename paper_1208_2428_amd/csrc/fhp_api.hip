@@ -101,17 +101,28 @@ Layout layout_for(uint32_t W, uint32_t H) {
 // limit.
 uint32_t default_depth(uint32_t wd) { return wd <= kMaxBlockedWords ? FHP_MAX_DEPTH : 1; }
 
-// Default band height of the blocked kernel: the largest even height up to 32
-// rows whose bands still give every SIMD a wave (a band's workgroup holds
-// ceil(wd / 64) waves).  Shorter bands cost halo work (1 + (K - 1) / T
-// level-rows per row), fewer waves leave SIMDs idle.  Measured at K = 5: on
-// 16384^2 (512 bands of four waves at 32 rows) 32 rows beat 24-64; on 4096^2
-// (one wave per band) 2, 4, 8, 16 and 32 rows ran 2.98e12, 3.61e12, 2.88e12,
-// 2.00e12 and 1.20e12 node-updates/s, and this rule picks 4.
+// Default band height of the blocked kernel, from occupancy: the largest even
+// height up to 32 rows whose bands give every SIMD two waves (a band's
+// workgroup holds ceil(wd / 64) waves); if that takes bands of 2 rows, the
+// largest that gives every SIMD one wave.  Shorter bands cost halo work
+// (1 + (K - 1) / T level-rows per row, K halo rows loaded on each side), fewer
+// waves leave SIMDs idle.  Measured at K = 5 (node-updates/s by band height):
+// 16384^2 (four waves per band) 32 rows 9.9e12, 24-64 rows 7.7e12-9.4e12;
+// 8192^2 (two) 4, 8, 16, 32 rows 5.10e12, 7.54e12, 5.37e12, 4.28e12; 4096^2
+// (one) 2, 4, 8, 32 rows 2.98e12, 3.61e12, 2.88e12, 1.20e12; 2048^2 (one, half
+// used) 2, 4 rows 1.14e12, 0.93e12.  The rule picks 32, 8, 4 and 2.
 uint32_t default_band(uint32_t H, uint32_t wd, uint32_t simds) {
     const uint64_t waves = (wd + 63) / 64;
-    uint32_t T = 32;
-    while (T > 2 && (uint64_t)((H + T - 1) / T) * waves < simds) T -= 2;
+    auto largest = [&](uint64_t need) -> uint32_t {  // 0 when no height gives `need` waves
+        for (uint32_t T = 32; T >= 2; T -= 2)
+            if ((uint64_t)((H + T - 1) / T) * waves >= need) return T;
+        return 0;
+    };
+    uint32_t T = largest(2ull * simds);
+    if (T < 4) {
+        const uint32_t T1 = largest(simds);
+        T = T1 > 2 ? T1 : 2;
+    }
     return H < T ? H : T;
 }
 
