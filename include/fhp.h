@@ -144,9 +144,10 @@ int fhp_set_depth(fhp_sim *s, uint32_t k);
 int fhp_get_depth(const fhp_sim *s, uint32_t *k);
 
 /* Rows per workgroup band of the blocked kernel (0 = library default: the
- * largest even height up to 32 whose bands give every SIMD of the device a
- * wave).  Each band also reads K halo rows above and below it.  Results do
- * not depend on it.  FHP_E_INVAL above the lattice height. */
+ * largest even height up to 32 whose bands give every SIMD of the device two
+ * waves, or one where two would take bands of 2 rows).  Each band also reads
+ * K halo rows above and below it.  Results do not depend on it.  FHP_E_INVAL
+ * above the lattice height. */
 int fhp_set_band(fhp_sim *s, uint32_t rows);
 
 /* Advances n steps (Sec. 2: motion then scattering, each step).  Asynchronous:
