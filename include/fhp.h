@@ -204,7 +204,9 @@ int fhp_batch_create(const fhp_params *ps, uint32_t n, void *dev_ws, size_t ws_b
                      void *hip_stream, fhp_batch **out);
 
 /* Tiling of the batch kernel: depth K (0 = FHP_BATCH_MAX_DEPTH), target band height
- * (0 = 32; per member the largest even divisor of H not above it and >= K),
+ * (0 = from occupancy: the largest even target up to 32 whose bands give every
+ * SIMD two waves, else one, else the one with most waves; per member the
+ * largest even divisor of H not above it and >= K),
  * threads per workgroup (0 = smallest multiple of 64 holding the widest row),
  * passes per launch (1 = one launch per pass; 0 = all passes of an
  * fhp_batch_step call in one launch, ordered by per-band dependencies).

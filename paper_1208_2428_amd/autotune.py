@@ -19,7 +19,7 @@ import torch
 
 DEFAULT_BATCH_CANDIDATES = [
     dict(depth=k, band=b, group_threads=nt, passes_per_launch=ppl)
-    for k in (4, 5) for b in (32, 64) for nt in (64, 256) for ppl in (1, 0)
+    for k in (4, 5) for b in (8, 16, 32, 64) for nt in (64, 256) for ppl in (1, 0)
 ]
 DEFAULT_SIM_CANDIDATES = [dict(depth=k, band=b) for k in (1, 2, 3, 4, 5) for b in (4, 8, 16, 32, 64)]
 
