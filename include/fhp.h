@@ -308,6 +308,46 @@ int fhp_pool_sync(fhp_pool *pl);
 /* Releases the pool (not the arena). */
 void fhp_pool_destroy(fhp_pool *pl);
 
+/* ---------------------------------------------------------------------------
+ * Allocation-free stepping, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.
+ * ------------------------------------------------------------------------- */
+
+/* Largest state (seven bit-planes) fhp_step_noalloc takes: 64 MiB, i.e.
+ * W*H <= 76,695,844 nodes (8192 x 8192 fits).  The library keeps a device
+ * array of this size on every GPU it runs on until the process ends. */
+#define FHP_NOALLOC_MAX_STATE_BYTES (64u << 20)
+
+/* Advances a lattice whose state at time t is in dev_in by n steps and writes
+ * the state at time t + n to dev_out, with the kernels of fhp_step and the
+ * same results bit for bit.  Enqueued on hip_stream (NULL = default stream);
+ * allocates nothing, neither on the host nor on the device: runs of more than
+ * one pass keep the state between passes in a library-owned device array.
+ *   p:         the lattice's parameters (seed, force_rate, walls, chirality,
+ *              rules; fill is unused); p->solid must be NULL;
+ *   dev_in:    device, 256-byte aligned, 7 planes of H * (W/64) uint64 words
+ *              each, packed (plane c at word c*H*(W/64), row y of a plane at
+ *              word y*(W/64), bit b of word w is node x = 64w + b); read only;
+ *   dev_out:   device, 256-byte aligned, the same layout; must not overlap
+ *              dev_in (n = 0 copies dev_in);
+ *   dev_solid: device, H * (W/64) uint64 words, bit set = obstacle node, or
+ *              NULL for none; FHP_WALLS_CHANNEL adds rows 0 and H-1;
+ *   t:         steps already done (the hash counters use it);
+ *   depth:     steps per pass as for fhp_set_depth (0 = default).
+ * All buffers stay the caller's and must stay alive until the work has run.
+ * Errors: FHP_E_INVAL for bad parameters or pointers, FHP_E_NOMEM for a state
+ * above FHP_NOALLOC_MAX_STATE_BYTES, FHP_E_STATE if t + n would reach 2^24,
+ * FHP_E_DEVICE for a HIP error; nothing is enqueued on an error.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time on
+ * one GPU (other streams, other threads) race; enqueue them on one stream.
+ * The array keeps the last call's contents, and no call reads what it has not
+ * written itself.  The first call on each GPU looks up the array's address:
+ * make it outside graph capture. */
+int fhp_step_noalloc(const fhp_params *p, const uint64_t *dev_in, uint64_t *dev_out,
+                     const uint64_t *dev_solid, uint64_t t, uint64_t n, uint32_t depth,
+                     void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

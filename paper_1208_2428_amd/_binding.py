@@ -106,7 +106,12 @@ _SIGNATURES = {
                                       ctypes.POINTER(ctypes.c_size_t)]),
     "fhp_pool_sync": (ctypes.c_int, [ctypes.c_void_p]),
     "fhp_pool_destroy": (None, [ctypes.c_void_p]),
+    "fhp_step_noalloc": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
+                                        ctypes.c_uint32, ctypes.c_void_p]),
 }
+
+NOALLOC_MAX_STATE_BYTES = 64 << 20
 
 
 def lib_path() -> str:

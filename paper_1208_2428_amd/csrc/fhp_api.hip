@@ -126,6 +126,26 @@ uint32_t default_band(uint32_t H, uint32_t wd, uint32_t simds) {
     return H < T ? H : T;
 }
 
+Dyn dyn_for(const fhp_params* p) {
+    Dyn D;
+    D.key_chir = hash64(p->seed, kTagChir);
+    D.key_force = hash64(p->seed, kTagForce);
+    D.thr_force = (uint64_t)floor(p->force_rate * 274877906944.0);  // f * 2^38
+    D.chir_mode = p->chirality;
+    D.rules = p->rules;
+    return D;
+}
+
+uint32_t device_simds() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
+        (void)hipGetLastError();  // not left for the next launch check to report
+        cus = 256;                // the MI355X's compute units
+    }
+    return 4 * (uint32_t)cus;
+}
+
 Lattice lattice_of(const fhp_sim* s) {
     Lattice L = s->L;
     L.S = s->has_mask ? s->S : nullptr;
@@ -149,20 +169,10 @@ int sim_setup(fhp_sim* s, const fhp_params* p, uint64_t* planes, const Layout& l
     s->L.wd = p->width / 64;
     s->L.ps = lay.plane_words;
     s->L.walls = p->walls == FHP_WALLS_CHANNEL;
-    s->D.key_chir = hash64(p->seed, kTagChir);
-    s->D.key_force = hash64(p->seed, kTagForce);
-    s->D.thr_force = (uint64_t)floor(p->force_rate * 274877906944.0);  // f * 2^38
-    s->D.chir_mode = p->chirality;
-    s->D.rules = p->rules;
+    s->D = dyn_for(p);
     s->depth = default_depth(s->L.wd);
     s->band = 0;
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
-        (void)hipGetLastError();  // not left for the next launch check to report
-        cus = 256;                // the MI355X's compute units
-    }
-    s->simds = 4 * (uint32_t)cus;
+    s->simds = device_simds();
 
     FHP_HIP_TRY(launch_fill_u64(s->S, lay.plane_words, 0, st), "clear solid plane");
     s->has_mask = 0;

@@ -56,6 +56,10 @@ int validate(const fhp_params* p);
 Layout layout_for(uint32_t W, uint32_t H);
 uint32_t default_depth(uint32_t wd);
 uint32_t default_band(uint32_t H, uint32_t wd, uint32_t simds);
+// Hash keys, forcing threshold and modes of the dynamics of *p.
+Dyn dyn_for(const fhp_params* p);
+// SIMDs of the current device (4 per compute unit).
+uint32_t device_simds();
 
 // Kernel launchers (fhp_kernels.hip).  All enqueue on `st` and return the HIP
 // launch status.

@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1208_2428_amd import _binding as B
@@ -122,3 +123,26 @@ def test_rule_set_checks(lib):
     assert lib.fhp_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == B.E_INVAL
     assert b"rule set" in lib.fhp_last_error()
     assert lib.fhp_pool_set_rules(None, B.RULES_FHP1) == B.E_INVAL
+
+
+def test_step_noalloc_argument_checks(lib):
+    """fhp_step_noalloc rejects what it cannot run before touching the device
+    (the pointers below are never dereferenced)."""
+    x, y = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20)
+    W, H = 8192, 9400  # 7 planes of 77M nodes: above the 64 MiB limit
+    assert 7 * W * H // 8 > B.NOALLOC_MAX_STATE_BYTES
+    p, _ = B.make_params(W, H)
+    assert lib.fhp_step_noalloc(ctypes.byref(p), x, y, None, 0, 5, 0, None) == B.E_NOMEM
+    assert b"at most" in lib.fhp_last_error()
+    p, _ = B.make_params(128, 8)
+    assert lib.fhp_step_noalloc(ctypes.byref(p), x, x, None, 0, 5, 0, None) == B.E_INVAL
+    assert lib.fhp_step_noalloc(ctypes.byref(p), x, ctypes.c_void_p((1 << 20) + 8), None,
+                                0, 5, 0, None) == B.E_INVAL  # overlapping
+    assert lib.fhp_step_noalloc(ctypes.byref(p), ctypes.c_void_p((1 << 20) + 8), y, None,
+                                0, 5, 0, None) == B.E_INVAL  # misaligned
+    assert lib.fhp_step_noalloc(ctypes.byref(p), x, y, None, 0, 5, 6, None) == B.E_INVAL
+    assert lib.fhp_step_noalloc(ctypes.byref(p), x, y, None, (1 << 24) - 2, 5, 0,
+                                None) == B.E_STATE
+    mask = np.zeros((8, 128), np.uint8)
+    p, keep = B.make_params(128, 8, solid=mask)
+    assert lib.fhp_step_noalloc(ctypes.byref(p), x, y, None, 0, 5, 0, None) == B.E_INVAL
