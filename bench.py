@@ -53,13 +53,19 @@ def recorded_traffic(name: str, depth: int):
     return traffic
 
 
-def cpu_baseline(wl, mask, seconds: float):
-    """Times the CPU oracle on a bounded sample of the workload: a full-width
-    band of 1024 rows of the same lattice (same mask rows, fill and forcing),
-    stepped until `seconds` have elapsed, on all host cores (capped at 16)."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_band_rate(wl, mask, rows: int, threads: int, seconds: float):
     import oracle
-    threads = oracle.default_threads()
-    rows = min(1024, wl.height)
     band = mask[:rows] if mask is not None else None
     state = oracle.init(wl.width, rows, wl.seed, wl.fill, mask=band, walls=wl.walls)
     steps, t0 = 0, time.perf_counter()
@@ -69,10 +75,29 @@ def cpu_baseline(wl, mask, seconds: float):
         el = time.perf_counter() - t0
         if el >= seconds:
             break
-    rate = wl.width * rows * steps / el
+    return wl.width * rows * steps / el, steps, el
+
+
+def cpu_baseline(wl, mask, seconds: float):
+    """Times the CPU oracle on bounded samples of the workload: a full-width
+    band of 1024 rows of the same lattice (same mask rows, fill and forcing)
+    on every core this process may use (the affinity set, capped by
+    OMP_NUM_THREADS when that is set), and a band of 64 rows on one core,
+    each stepped until its share of `seconds` has elapsed."""
+    import oracle
+    threads = oracle.default_threads()
+    rows = min(1024, wl.height)
+    rate, steps, el = _oracle_band_rate(wl, mask, rows, threads, seconds * 2 / 3)
+    rows1 = min(64, wl.height)
+    rate1, steps1, el1 = _oracle_band_rate(wl, mask, rows1, 1, seconds / 3)
     return {"value": rate, "unit": "node-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{wl.width}x{rows} band (rows 0-{rows - 1}) of {wl.name}, "
-                      f"{steps} steps in {el:.1f} s"}
+                      f"{steps} steps in {el:.1f} s on {threads} threads",
+            "single_core": {"value": rate1, "cores": 1,
+                            "sample": f"{wl.width}x{rows1} band (rows 0-{rows1 - 1}), "
+                                      f"{steps1} steps in {el1:.1f} s"},
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0))}
 
 
 VALU_WAVE_INSTR_PEAK = 256 * 4 * 2.4e9 / 4  # SIMDs x clock / 4 cycles per wave64 instruction
@@ -91,106 +116,135 @@ def recorded_valu(name: str, depth: int):
     return insts
 
 
-def depth_sweep(wl, mask, steps: int):
+def depth_sweep(wl, mask, min_seconds: float):
     """Throughput and HBM roofline fraction of the single-lattice kernel at
-    every depth (the fraction of 14/K bits per node-step falls with K by
-    construction; the HBM-bound regime is K <= 2)."""
+    every depth, each timed with HIP events over at least `min_seconds` (the
+    fraction of 14/K bits per node-step falls with K by construction)."""
     from paper_1208_2428_amd import _binding as B
     out = []
     for k in range(1, B.MAX_DEPTH + 1):
-        n = steps - steps % k
-        v = plain_rate(wl, mask, k, n)
+        v, n = plain_rate(wl, mask, k, min_seconds)
         frac = v * PLANE_BITS / k / 8 / 1e9 / HBM_PEAK_GBS
         out.append({"depth": k, "value": v, "frac": frac, "steps": n})
-        log(f"bench: depth {k}: {v:.3e} node-updates/s, {frac:.3f} of the HBM roofline")
+        log(f"bench: depth {k}: {v:.3e} node-updates/s over {n} steps, "
+            f"{frac:.3f} of the HBM roofline")
     return out
 
 
-def plain_rate(wl, mask, depth: int, steps: int) -> float:
-    """Node updates/s of the single-lattice kernel at depth `depth`, timed
-    with HIP events on the stream the kernels run on (after one untimed run
-    of the same length)."""
+def plain_rate(wl, mask, depth: int, min_seconds: float = 0.1):
+    """(node updates/s, steps timed) of the single-lattice kernel at depth
+    `depth`: a short untimed run sizes the measurement, which is then timed
+    with HIP events on the stream the kernels run on over at least
+    `min_seconds`, after an untimed run of the same length."""
     import torch
 
     from paper_1208_2428_amd import Sim
     from paper_1208_2428_amd.autotune import time_steps
     sim = Sim(**wl.params(), solid=mask, depth=depth)
-    per_step = time_steps(sim.step, torch.cuda.current_stream(), steps, 1)
+    probe = time_steps(sim.step, torch.cuda.current_stream(), 12 * depth, 1)
+    n = max(depth, int(min_seconds / probe) + 1)
+    n = (n + depth - 1) // depth * depth
+    per_step = time_steps(sim.step, torch.cuda.current_stream(), n, 1)
     sim.close()
-    return wl.width * wl.height / per_step
+    return wl.width * wl.height / per_step, n
 
 
-def batched_leg(args, wl, mask, depth, value):
-    """512 uneven lattices in one batch vs the plain single-lattice kernel."""
+def golden_ensemble():
+    """Oracle digests of the ensemble members after its 500 steps, by index
+    (written by tests/golden/make_golden.py ensemble-512), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "digests_ensemble-512.txt")
+    if not os.path.exists(path):
+        return None
+    out = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                f = line.split()
+                out[int(f[0])] = int(f[4], 16)
+    return out
+
+
+def batched_leg(args, plain_at):
+    """512 uneven lattices in one batch vs the plain single-lattice kernel at
+    the same depth; every member's digest against the same lattice stepped
+    alone and against the oracle's."""
     from paper_1208_2428_amd import ensemble
     params = ensemble.ensemble_params()
     log(f"bench: ensemble of {len(params)} lattices, {args.ensemble_steps} steps (tuning first)")
     res = ensemble.run_batched(params, args.ensemble_steps, log=log)
     k = res["tiling"]["depth"]
-    plain = value if k == depth else plain_rate(wl, mask, k, 480)
+    plain = plain_at(k)
     log(f"bench: ensemble {res['value']:.3e} node-updates/s at depth {k}; plain {plain:.3e}")
     one = ensemble.run_one_by_one(params, args.ensemble_steps)
     log(f"bench: ensemble one lattice at a time: {one['value']:.3e} node-updates/s")
+    same = sum(a == b for a, b in zip(res["digests"], one["digests"]))
+    gold = golden_ensemble() if args.ensemble_steps == 500 else None
+    vs_oracle = None
+    if gold is not None and len(gold) == len(params):
+        vs_oracle = sum(res["digests"][i] == gold[i] for i in range(len(params)))
+    log(f"bench: ensemble digests: {same}/{len(params)} equal to the lattices stepped alone, "
+        f"{'n/a' if vs_oracle is None else vs_oracle}/{len(params)} equal to the oracle's")
+    parity = same == len(params) and (vs_oracle is None or vs_oracle == len(params))
     return {"value": res["value"], "unit": "node-updates/s", "lattices": res["lattices"],
             "nodes": res["nodes"], "steps": res["steps"], "tiling": res["tiling"],
+            "timing": "HIP events on the batch stream, graph replay, median of "
+                      f"{len(res['seconds_all'])} runs of {res['steps']} steps",
             "plain_value_same_depth": plain, "ratio_vs_plain": res["value"] / plain,
-            "ratio_vs_headline": res["value"] / value,
-            "one_by_one_value": one["value"], "ratio_vs_one_by_one": res["value"] / one["value"]}
+            "one_by_one_value": one["value"], "ratio_vs_one_by_one": res["value"] / one["value"],
+            "members_equal_alone": same, "members_equal_oracle": vs_oracle, "parity": parity}
 
 
-def rules_leg(args, wl, mask, plain):
+def rules_leg(args, wl, mask, plain_at):
     """The headline workload under the other rule sets (FHP-I, FHP-III), each
-    at its default depth: throughput and per-launch HBM roofline fraction."""
+    at its default depth: throughput (HIP events) and per-launch HBM roofline
+    fraction, against FHP-II at the same depth."""
     import torch
 
     from paper_1208_2428_amd import Sim
     from paper_1208_2428_amd import _binding as B
+    from paper_1208_2428_amd.autotune import time_steps
     stream = torch.cuda.current_stream()
     nodes = wl.width * wl.height
     out = {}
     for name, rules, max_depth in (("fhp1", B.RULES_FHP1, B.MAX_DEPTH), ("fhp3", B.RULES_FHP3, 3)):
         sim = Sim(**wl.params(), solid=mask, rules=rules)
         depth = min(sim.depth, max_depth)  # steps per launch
-        sim.step(8 * depth)
-        torch.cuda.synchronize()
-        steps = args.rules_steps
-        t0 = time.perf_counter()
-        sim.step(steps)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        launches = 50
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(launches)]
-        for a, b in evs:
-            a.record(stream)
-            sim.step(depth)
-            b.record(stream)
-        torch.cuda.synchronize()
-        launch_s = sum(a.elapsed_time(b) for a, b in evs) / launches / 1e3
+        sim.depth = depth
+        steps = args.rules_steps - args.rules_steps % depth
+        per_step = time_steps(sim.step, stream, steps, 1)
+        launch_s = launch_seconds(sim, stream, depth, 200)
         sim.close()
         achieved = PLANE_BITS * nodes / 8 / launch_s / 1e9
-        value = nodes * steps / wall
+        value = nodes / per_step
+        fhp2 = plain_at(depth)
         out[name] = {"value": value, "unit": "node-updates/s", "depth": depth, "steps": steps,
-                     "ratio_vs_fhp2": value / plain, "kernel_us": launch_s * 1e6,
-                     "roofline_frac": achieved / HBM_PEAK_GBS}
-        log(f"bench: {name} {value:.3e} node-updates/s at depth {depth}")
+                     "fhp2_same_depth": fhp2, "ratio_vs_fhp2": value / fhp2,
+                     "kernel_us": launch_s * 1e6, "roofline_frac": achieved / HBM_PEAK_GBS}
+        log(f"bench: {name} {value:.3e} node-updates/s at depth {depth} "
+            f"(FHP-II {fhp2:.3e})")
     return out
 
 
-def served_leg(args, wl, mask, value, depth):
+def served_leg(args, plain_at, depth):
     """Continuous batching of a Poisson stream of channel-flow jobs, at the
-    deepest depth pools take; compared with the plain kernel at that depth."""
+    deepest depth pools take; compared with the plain kernel at that depth.
+    A seeded sample of the served jobs is run again alone: its 16 x 16 block
+    sums must equal what the server returned."""
+    import numpy as np
+
     from paper_1208_2428_amd import _binding as B
+    from paper_1208_2428_amd import Sim
     from paper_1208_2428_amd import serve
     from paper_1208_2428_amd import workloads as WL
-    sdepth = min(depth, B.BATCH_MAX_DEPTH)
-    plain = value if sdepth == depth else plain_rate(wl, mask, sdepth, 480)
-    depth = sdepth
+    depth = min(depth, B.BATCH_MAX_DEPTH)
+    plain = plain_at(depth)
     reqs = WL.request_stream(n=args.serve_requests, rate=200.0, seed=5)
     offered = serve.offered_load(reqs)
+    sample = sorted(int(i) for i in np.random.default_rng(7).choice(
+        len(reqs), size=min(args.serve_check, len(reqs)), replace=False))
     log(f"bench: serving {len(reqs)} requests at 200/s (offered {offered:.3e} node-updates/s)")
     srv = serve.Server(lattice_bytes=32 << 30, max_slots=512, passes_per_tick=1, depth=depth)
-    hot = srv.run(reqs, realtime=True, log=log)
+    hot = srv.run(reqs, realtime=True, keep_results=set(sample), log=log)
     log(f"bench: served {hot['completed']} in {hot['seconds']:.1f} s: {hot['value']:.3e} "
         f"node-updates/s, p50 {hot['p50_ms']:.0f} ms, p99 {hot['p99_ms']:.0f} ms")
     # a second point at about 80% of the measured capacity
@@ -200,15 +254,79 @@ def served_leg(args, wl, mask, value, depth):
     at80 = srv.run(reqs80, realtime=True, log=log)
     log(f"bench: at {rate80:.0f} req/s: p50 {at80['p50_ms']:.0f} ms, p99 {at80['p99_ms']:.0f} ms")
     srv.close()
+    same = 0
+    for i in sample:
+        r = reqs[i]
+        sim = Sim(**serve.job_params(r))
+        sim.step(r.steps)
+        same += int(np.array_equal(sim.observe_blocks(16), hot["results"][i]))
+        sim.close()
+    log(f"bench: {same}/{len(sample)} sampled served jobs equal to the same job run alone")
     keys = ("requests", "completed", "seconds", "value", "p50_ms", "p99_ms", "mean_ms",
             "max_queue", "max_resident", "ticks")
     return {"value": hot["value"], "unit": "node-updates/s", "depth": depth,
             "plain_value_same_depth": plain, "ratio_vs_plain": hot["value"] / plain,
-            "ratio_vs_headline": hot["value"] / value,
+            "timing": "wall clock from the first arrival to the last result on the host",
             "offered_load": offered, "rate_per_s": 200.0, "arena_bytes": 32 << 30,
             "overloaded": {k: hot[k] for k in keys},
             "at_80pct_capacity": dict({k: at80[k] for k in keys}, rate_per_s=rate80,
-                                      offered_load=serve.offered_load(reqs80))}
+                                      offered_load=serve.offered_load(reqs80)),
+            "sampled_jobs": len(sample), "sampled_equal_alone": same,
+            "parity": same == len(sample)}
+
+
+def launch_seconds(sim, stream, depth: int, launches: int) -> float:
+    """Average duration of one pass of `depth` steps (one kernel launch),
+    HIP events around each launch on the kernel's stream."""
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(launches)]
+    for a, b in evs:
+        a.record(stream)
+        sim.step(depth)
+        b.record(stream)
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in evs) / launches / 1e3
+
+
+def small_config(name: str, min_seconds: float):
+    """A smaller named workload run in full from its initial state (digest
+    against the oracle's at its last step), then timed with HIP events over
+    further runs of the same length until `min_seconds` have been covered."""
+    import torch
+
+    from paper_1208_2428_amd import Sim
+    from paper_1208_2428_amd import workloads as WL
+    wl = WL.WORKLOADS[name]
+    stream = torch.cuda.current_stream()
+    sim = Sim(**wl.params(), solid=wl.mask())
+    sim.step(wl.steps)
+    digest = sim.digest()
+    ref = golden_digest(name, wl.steps)
+    parity = None if ref is None else digest == ref
+    runs = 0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    while True:
+        sim.step(wl.steps)
+        runs += 1
+        if time.perf_counter() - t0 >= min_seconds:
+            break
+    e1.record(stream)
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    depth = sim.depth
+    sim.close()
+    value = wl.width * wl.height * wl.steps * runs / sec
+    log(f"bench: {name}: {value:.3e} node-updates/s at depth {depth} "
+        f"({runs} runs of {wl.steps} steps); digest at t={wl.steps} "
+        f"{'matches' if parity else 'DIFFERS FROM' if parity is False else 'has no'} oracle")
+    return {"value": value, "unit": "node-updates/s", "width": wl.width, "height": wl.height,
+            "steps": wl.steps, "depth": depth, "timed_steps": wl.steps * runs,
+            "fill": wl.fill, "force_rate": wl.force_rate, "walls": wl.walls,
+            "parity_digest_vs_oracle": parity}
 
 
 def main() -> int:
@@ -219,19 +337,26 @@ def main() -> int:
     ap.add_argument("--depth", type=int, default=0, help="temporal-block depth k (0 = default)")
     ap.add_argument("--band", type=int, default=0, help="rows per workgroup band (0 = default)")
     ap.add_argument("--workload", default="porous-16384")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--launches", type=int, default=200,
+                    help="launches timed one by one for the per-launch kernel time")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the 512-lattice batched ensemble comparison")
     ap.add_argument("--ensemble-steps", type=int, default=500)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop leg")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-check", type=int, default=32,
+                    help="served jobs run again alone and compared")
     ap.add_argument("--no-rules", action="store_true",
                     help="skip the FHP-I / FHP-III rule-set leg")
-    ap.add_argument("--rules-steps", type=int, default=400)
+    ap.add_argument("--rules-steps", type=int, default=3000)
     ap.add_argument("--no-depth-sweep", action="store_true",
                     help="skip the throughput / roofline sweep over depths 1..5")
-    ap.add_argument("--sweep-steps", type=int, default=240)
+    ap.add_argument("--sweep-seconds", type=float, default=0.1,
+                    help="HIP-event time covered at each depth of the sweep")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 256^2 torus and 4096^2 channel workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -277,20 +402,14 @@ def main() -> int:
     log(f"bench: digest at t={args.steps}: {digest:016x}, oracle {'n/a' if ref is None else f'{ref:016x}'}")
 
     # Per-launch duration of the step kernel, with events on the kernel's stream.
-    launches = max(1, min(200, args.steps // depth))
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(launches)]
-    for a, b in evs:
-        a.record(stream)
-        sim.step(depth)
-        b.record(stream)
-    torch.cuda.synchronize()
-    launch_s = sum(a.elapsed_time(b) for a, b in evs) / launches / 1e3
+    launch_s = launch_seconds(sim, stream, depth, args.launches)
     bytes_per_launch = PLANE_BITS * nodes / 8  # 14/k bits per node-step, k steps per launch
     achieved = bytes_per_launch / launch_s / 1e9
     sim.close()
     traffic = recorded_traffic(wl.name, depth)
     valu = recorded_valu(wl.name, depth)
+    log(f"bench: {args.launches} launches of depth {depth}: {launch_s * 1e6:.1f} us each, "
+        f"{achieved / HBM_PEAK_GBS:.3f} of the HBM roofline")
 
     value = nodes * args.steps / wall
     out = {
@@ -310,9 +429,11 @@ def main() -> int:
                    "fill": wl.fill, "force_rate": wl.force_rate,
                    "solid_fraction": round(solid_frac, 5), "depth": depth, "band": args.band,
                    "parity_digest_vs_oracle": parity},
+        "events_value": nodes * args.steps / ev_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel_us": launch_s * 1e6, "bytes_per_launch": bytes_per_launch},
+                     "kernel_us": launch_s * 1e6, "launches_timed": args.launches,
+                     "bytes_per_launch": bytes_per_launch},
     }
     if valu is not None:
         # the same launch against the VALU issue limit (wave64 instructions;
@@ -321,14 +442,25 @@ def main() -> int:
         out["alu"] = {"bound": "alu", "achieved": rate, "peak": VALU_WAVE_INSTR_PEAK,
                       "unit": "wave64 VALU instructions/s", "frac": rate / VALU_WAVE_INSTR_PEAK,
                       "valu_insts_per_launch": valu}
+    plain = {}
     if not args.no_depth_sweep:
-        out["depth_sweep"] = depth_sweep(wl, mask, args.sweep_steps)
+        out["depth_sweep"] = depth_sweep(wl, mask, args.sweep_seconds)
+        plain = {d["depth"]: d["value"] for d in out["depth_sweep"]}
+
+    def plain_at(k: int) -> float:
+        """The plain kernel's rate at depth k, HIP events over >= 100 ms."""
+        if k not in plain:
+            plain[k] = plain_rate(wl, mask, k, max(0.1, args.sweep_seconds))[0]
+        return plain[k]
+
+    if not args.no_configs:
+        out["configs"] = {n: small_config(n, 0.1) for n in ("torus-256", "channel-4096")}
     if not args.no_ensemble:
-        out["batched"] = batched_leg(args, wl, mask, depth, value)
+        out["batched"] = batched_leg(args, plain_at)
     if not args.no_serve:
-        out["served"] = served_leg(args, wl, mask, value, depth)
+        out["served"] = served_leg(args, plain_at, depth)
     if not args.no_rules:
-        out["rule_sets"] = rules_leg(args, wl, mask, value)
+        out["rule_sets"] = rules_leg(args, wl, mask, plain_at)
     if not args.no_cpu_baseline:
         log(f"bench: timing the CPU oracle for ~{args.cpu_seconds:.0f} s")
         out["cpu_baseline"] = cpu_baseline(wl, mask, args.cpu_seconds)

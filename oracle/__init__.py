@@ -97,7 +97,16 @@ def _check_state(state: np.ndarray) -> None:
 
 
 def default_threads() -> int:
-    return max(1, min(16, os.cpu_count() or 1))
+    """Every CPU this process may run on (its affinity set), capped by
+    OMP_NUM_THREADS when that is set (a host's share of CPUs per GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    omp = os.environ.get("OMP_NUM_THREADS", "")
+    if omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(1, n)
 
 
 def hash64(key: int, n: int) -> int:

@@ -6,10 +6,13 @@ Trials run on the caller's lattices (they advance them; callers that need the
 initial state create a fresh batch afterwards).  Timing uses HIP events
 recorded on the stream the kernels run on.  The cache is a JSON file
 (``$FHP_TUNE_CACHE``, default ``~/.cache/paper_1208_2428_amd/tune.json``)
-keyed by the GPU name and a signature of the workload.
+keyed by the GPU name, a signature of the workload (sizes, rule set, forcing,
+obstacles, walls), a hash of the candidate list and a hash of the kernel
+sources, so that a choice made for other kernels or candidates is never reused.
 """
 from __future__ import annotations
 
+import glob
 import hashlib
 import json
 import os
@@ -19,7 +22,7 @@ import torch
 
 DEFAULT_BATCH_CANDIDATES = [
     dict(depth=k, band=b, group_threads=nt, passes_per_launch=ppl)
-    for k in (4, 5) for b in (8, 16, 32, 64) for nt in (64, 256) for ppl in (1, 0)
+    for k in (1, 2, 3, 4, 5) for b in (8, 16, 32, 64) for nt in (64, 256) for ppl in (1, 0)
 ]
 DEFAULT_SIM_CANDIDATES = [dict(depth=k, band=b) for k in (1, 2, 3, 4, 5) for b in (4, 8, 16, 32, 64)]
 
@@ -56,11 +59,33 @@ def _gpu_name() -> str:
     return torch.cuda.get_device_name(torch.cuda.current_device())
 
 
+_SOURCES_HASH = None
+
+
+def sources_hash() -> str:
+    """Hash of every kernel source file of the library."""
+    global _SOURCES_HASH
+    if _SOURCES_HASH is None:
+        h = hashlib.sha1()
+        csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+        for path in sorted(glob.glob(os.path.join(csrc, "*.h")) + glob.glob(os.path.join(csrc, "*.hip"))):
+            h.update(os.path.basename(path).encode())
+            with open(path, "rb") as fh:
+                h.update(fh.read())
+        _SOURCES_HASH = h.hexdigest()[:12]
+    return _SOURCES_HASH
+
+
+def _candidates_hash(candidates) -> str:
+    return hashlib.sha1(json.dumps(candidates, sort_keys=True).encode()).hexdigest()[:12]
+
+
 def batch_signature(params: list[dict]) -> str:
     sizes = Counter((p["width"], p["height"]) for p in params)
     flags = (any(p.get("force_rate", 0) > 0 for p in params),
              any(p.get("solid") is not None for p in params),
-             any(p.get("walls", False) for p in params))
+             any(p.get("walls", False) for p in params),
+             sorted({int(p.get("rules", 0)) for p in params}))
     text = json.dumps([sorted(sizes.items()), flags])
     return hashlib.sha1(text.encode()).hexdigest()[:16]
 
@@ -85,7 +110,8 @@ def tune_batch(batch, params: list[dict], candidates=None, steps: int = 24,
                use_cache: bool = True) -> dict:
     """Returns {"tiling": best candidate, "trials": [(candidate, s/step)]} and
     leaves `batch` set to the best tiling."""
-    key = f"batch:{_gpu_name()}:{batch_signature(params)}"
+    key = (f"batch:{_gpu_name()}:{batch_signature(params)}:"
+           f"{_candidates_hash(DEFAULT_BATCH_CANDIDATES)}:{sources_hash()}")
     if use_cache and candidates is None:
         hit = _load_cache().get(key)
         if hit:
@@ -109,7 +135,8 @@ def tune_batch(batch, params: list[dict], candidates=None, steps: int = 24,
 
 def tune_sim(sim, candidates=None, steps: int = 48, use_cache: bool = True) -> dict:
     """Tunes depth and band of a standalone simulation (advances it)."""
-    key = f"sim:{_gpu_name()}:{sim.width}x{sim.height}"
+    sig = json.dumps([sim.width, sim.height, sim.rules, sim.force_rate > 0, sim.has_mask, sim.walls])
+    key = f"sim:{_gpu_name()}:{sig}:{_candidates_hash(DEFAULT_SIM_CANDIDATES)}:{sources_hash()}"
     if use_cache and candidates is None:
         hit = _load_cache().get(key)
         if hit:

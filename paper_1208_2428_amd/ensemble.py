@@ -4,8 +4,6 @@ sides uniform over the multiples of 64 in [128, 2048], fill uniform in
 graph replay, tiling from the autotuner)."""
 from __future__ import annotations
 
-import time
-
 import torch
 
 from . import autotune
@@ -19,9 +17,17 @@ def ensemble_params(n: int = 512, seed: int = 4) -> list[dict]:
             for m in WL.batch_members(n=n, seed=seed)]
 
 
-def run_batched(params: list[dict], steps: int, tiling: dict | None = None, log=None) -> dict:
-    """Times `steps` steps of the whole ensemble from its initial state.
-    With no tiling given, tunes on a scratch batch first."""
+def run_batched(params: list[dict], steps: int, tiling: dict | None = None, log=None,
+                repeats: int = 3) -> dict:
+    """Times `steps` steps of the whole ensemble and returns every member's
+    state digest after `steps` steps from its initial state.
+
+    With no tiling given, tunes on a scratch batch first.  The timed batch
+    first makes one untimed call of `steps` steps, which captures and
+    instantiates its graph; each of the `repeats` timed calls then replays
+    that graph (HIP events on the batch's stream; the median is reported).
+    A second batch, advanced `steps` steps from the initial state with the
+    same tiling, gives the digests."""
     if tiling is None:
         scratch = Batch(params)
         res = autotune.tune_batch(scratch, params)
@@ -31,38 +37,53 @@ def run_batched(params: list[dict], steps: int, tiling: dict | None = None, log=
         if log:
             log(f"ensemble: tuned tiling {tiling}")
     b = Batch(params, **tiling)
-    # capture the launch sequence once on a scratch run of the same length
-    warm = Batch(params, **tiling)
-    warm.step(steps)
-    warm.sync()
-    warm.close()
-    del warm
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.step(steps)
+    b.step(steps)  # captures the graph of this launch sequence
     b.sync()
-    wall = time.perf_counter() - t0
-    nodes = sum(p["width"] * p["height"] for p in params)
-    out = {"value": nodes * steps / wall, "unit": "node-updates/s", "seconds": wall,
-           "steps": steps, "lattices": len(params), "nodes": nodes, "tiling": tiling}
+    times = []
+    for _ in range(max(1, repeats)):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(b.stream)
+        b.step(steps)
+        e1.record(b.stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    b.sync()
     b.close()
-    return out
+    del b
+    fresh = Batch(params, **tiling)
+    fresh.step(steps)
+    fresh.sync()
+    digests = [fresh[i].digest() for i in range(len(params))]
+    fresh.close()
+    sec = sorted(times)[len(times) // 2]
+    nodes = sum(p["width"] * p["height"] for p in params)
+    return {"value": nodes * steps / sec, "unit": "node-updates/s", "seconds": sec,
+            "seconds_all": times, "steps": steps, "lattices": len(params), "nodes": nodes,
+            "tiling": tiling, "digests": digests}
 
 
 def run_one_by_one(params: list[dict], steps: int, depth: int = 0) -> dict:
     """The same ensemble as standalone simulations, each stepped with its own
-    launches, one after the other on one stream."""
+    launches, one after the other on one stream; also returns every member's
+    digest after `steps` steps."""
     sims = [Sim(**p, depth=depth) for p in params]
+    stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
     for s in sims:
         s.step(steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    e1.record(stream)
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
     nodes = sum(p["width"] * p["height"] for p in params)
+    digests = [s.digest() for s in sims]
     for s in sims:
         s.close()
-    return {"value": nodes * steps / wall, "unit": "node-updates/s", "seconds": wall}
+    return {"value": nodes * steps / sec, "unit": "node-updates/s", "seconds": sec,
+            "digests": digests}
 
 
 def main(argv=None) -> int:

@@ -34,6 +34,8 @@ class Sim:
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)
         self.width, self.height = int(width), int(height)
+        self.rules, self.force_rate, self.walls = int(rules), float(force_rate), bool(walls)
+        self.has_mask = solid is not None
         params, keep = B.make_params(width, height, seed, fill, force_rate, walls, chirality, solid,
                                      rules)
         nbytes = B.workspace_bytes(params)

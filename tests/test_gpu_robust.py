@@ -1,0 +1,115 @@
+"""Checkpoint/resume and cancellation on the GPU.
+
+Checkpoint: the state saved after n1 steps (n1 not a multiple of the depth)
+through fhp_get_state, restored into a fresh handle with fhp_set_state at
+time n1, then advanced n2 more steps, must equal n1 + n2 uninterrupted steps
+(and the oracle's), bit for bit: the paper's byte layout carries everything
+the dynamics needs, and the hash keys on (t, y, word) only.
+
+Cancellation: a pool job released while it still has steps left frees its
+memory for the next job; the jobs that stay resident are unaffected.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1208_2428_amd import Pool, Sim
+from paper_1208_2428_amd import serve
+from paper_1208_2428_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+THREADS = oracle.default_threads()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("depth,n1,n2,rules", [(5, 13, 22, 0), (5, 7, 9, 1), (3, 4, 11, 2),
+                                               (4, 1, 30, 0)])
+def test_checkpoint_resume_equals_uninterrupted(depth, n1, n2, rules):
+    say("checkpoint", depth, n1, n2, rules)
+    W, H = 1024, 258
+    mask = WL.porous_mask(W, H, seed=21, rmin=4, rmax=9, frac=0.06)
+    kw = dict(seed=77, fill=0.3, force_rate=4e-3, walls=True, solid=mask, rules=rules)
+    whole = Sim(W, H, depth=depth, **kw)
+    whole.step(n1 + n2)
+    ref_state = whole.get_state()
+    ref_digest = whole.digest()
+    whole.close()
+
+    first = Sim(W, H, depth=depth, **kw)
+    first.step(n1)
+    saved = first.get_state()
+    assert first.t == n1
+    first.close()
+
+    # a fresh handle with no obstacle mask and no particles: bit 7 of the
+    # checkpoint brings the obstacles back
+    resumed = Sim(W, H, depth=depth, **dict(kw, fill=0.0, solid=None))
+    resumed.set_state(saved, t=n1)
+    assert resumed.t == n1
+    resumed.step(n2)
+    assert resumed.t == n1 + n2
+    np.testing.assert_array_equal(resumed.get_state(), ref_state)
+    assert resumed.digest() == ref_digest
+    resumed.close()
+
+    st = oracle.init(W, H, 77, 0.3, mask=mask, walls=True)
+    st, _ = oracle.run(st, 0, n1 + n2, 77, 4e-3, threads=THREADS, rules=rules)
+    np.testing.assert_array_equal(ref_state, st)
+
+
+def test_checkpoint_across_depths():
+    """A checkpoint written at one depth resumes at another."""
+    W, H = 512, 130
+    kw = dict(seed=5, fill=0.25, force_rate=1e-3, walls=True)
+    a = Sim(W, H, depth=5, **kw)
+    a.step(12)
+    saved = a.get_state()
+    a.step(17)
+    ref = a.get_state()
+    b = Sim(W, H, depth=2, **kw)
+    b.set_state(saved, t=12)
+    b.step(17)
+    np.testing.assert_array_equal(b.get_state(), ref)
+
+
+def test_released_job_frees_memory_and_survivors_are_unaffected():
+    side = 384
+    lattice = 4 * serve.job_bytes(side)
+    pool = Pool(Pool.arena_bytes_for(8, 4096, lattice), max_slots=8, max_bands=4096, depth=5)
+    jobs = [dict(width=side, height=side, seed=40 + k, fill=0.25, force_rate=1e-3, walls=True)
+            for k in range(5)]
+    steps = [60, 200, 45, 33, 200]
+    slots = [pool.admit(steps[k], **jobs[k]) for k in range(4)]
+    assert None not in slots
+    assert pool.admit(steps[4], **jobs[4]) is None  # the arena holds four
+    pool.tick(2)
+    pool.tick(1)
+    used = pool.usage()["bytes_used"]
+    pool.release(slots[1])  # 200 steps asked, 15 done: cancelled
+    assert pool.usage()["bytes_used"] < used
+    s4 = pool.admit(steps[4], **jobs[4])  # takes the freed memory
+    assert s4 is not None
+    slot_job = {slots[0]: 0, slots[2]: 2, slots[3]: 3, s4: 4}
+    got = {}
+    for _ in range(1000):
+        if len(got) == len(slot_job):
+            break
+        pool.tick(1)
+        for s in pool.done():
+            got[slot_job[s]] = pool.member(s).get_state()
+            pool.release(s)
+    assert sorted(got) == [0, 2, 3, 4]
+    for k in got:
+        alone = Sim(**jobs[k])
+        alone.step(steps[k])
+        np.testing.assert_array_equal(got[k], alone.get_state(), err_msg=f"job {k}")
+        alone.close()
+    st = oracle.init(side, side, jobs[3]["seed"], 0.25, walls=True)
+    st, _ = oracle.run(st, 0, steps[3], jobs[3]["seed"], 1e-3, threads=THREADS)
+    np.testing.assert_array_equal(got[3], st)
+    assert pool.usage()["active"] == 0
+    pool.close()
