@@ -100,6 +100,47 @@ def cpu_baseline(wl, mask, seconds: float):
             "affinity_cpus": len(os.sched_getaffinity(0))}
 
 
+def cpu_simd_baseline(wl, mask, seconds: float):
+    """The host bit-plane stepper (SIMD along rows, OpenMP over rows; the
+    counterpart of the paper's pSSE/pAVX codes) on the same bounded samples
+    as the oracle baseline, all allotted cores and one core; its digest of
+    the 256^2 torus workload is checked against the oracle's."""
+    import oracle
+    from paper_1208_2428_amd import cpu_sim
+    from paper_1208_2428_amd import workloads as WL
+
+    def rate(rows, threads, budget):
+        band = mask[:rows] if mask is not None else None
+        s = cpu_sim.CpuSim(wl.width, rows, seed=wl.seed, fill=wl.fill, force_rate=wl.force_rate,
+                           walls=wl.walls, solid=band)
+        s.step(2, threads)
+        steps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < budget:
+            s.step(10, threads)
+            steps += 10
+        el = time.perf_counter() - t0
+        s.close()
+        return wl.width * rows * steps / el, steps, el
+
+    threads = oracle.default_threads()
+    rows = min(1024, wl.height)
+    v, steps, el = rate(rows, threads, seconds * 2 / 3)
+    v1, steps1, el1 = rate(min(256, wl.height), 1, seconds / 3)
+    tw = WL.WORKLOADS["torus-256"]
+    t = cpu_sim.CpuSim(**tw.params())
+    t.step(tw.steps, threads)
+    ref = golden_digest(tw.name, tw.steps)
+    parity = None if ref is None else t.digest() == ref
+    t.close()
+    log(f"bench: CPU bit-plane stepper ({cpu_sim.isa()}): {v:.3e} node-updates/s on {threads} "
+        f"threads, {v1:.3e} on one")
+    return {"value": v, "unit": "node-updates/s", "cores": threads, "kind": "bit-plane SIMD",
+            "isa": cpu_sim.isa(), "sample": f"{wl.width}x{rows} band of {wl.name}, {steps} steps "
+                                            f"in {el:.1f} s on {threads} threads",
+            "single_core": {"value": v1, "cores": 1, "steps": steps1, "seconds": el1},
+            "cpu_model": cpu_model(), "parity_torus-256_digest_vs_oracle": parity}
+
+
 VALU_WAVE_INSTR_PEAK = 256 * 4 * 2.4e9 / 4  # SIMDs x clock / 4 cycles per wave64 instruction
 
 
@@ -341,6 +382,9 @@ def main() -> int:
                     help="launches timed one by one for the per-launch kernel time")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-simd", action="store_true",
+                    help="skip the host bit-plane stepper baseline")
+    ap.add_argument("--cpu-simd-seconds", type=float, default=6.0)
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the 512-lattice batched ensemble comparison")
     ap.add_argument("--ensemble-steps", type=int, default=500)
@@ -464,6 +508,8 @@ def main() -> int:
     if not args.no_cpu_baseline:
         log(f"bench: timing the CPU oracle for ~{args.cpu_seconds:.0f} s")
         out["cpu_baseline"] = cpu_baseline(wl, mask, args.cpu_seconds)
+    if not args.no_cpu_simd:
+        out["cpu_simd_baseline"] = cpu_simd_baseline(wl, mask, args.cpu_simd_seconds)
     print(json.dumps(out), flush=True)
     return 0
 
