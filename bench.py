@@ -317,17 +317,39 @@ def served_leg(args, plain_at, depth):
 
 
 def launch_seconds(sim, stream, depth: int, launches: int) -> float:
-    """Average duration of one pass of `depth` steps (one kernel launch),
-    HIP events around each launch on the kernel's stream."""
+    """Average duration of one pass of `depth` steps (one kernel launch):
+    `launches` passes back to back between two HIP events on the kernel's
+    stream, divided by their number (so the few microseconds between
+    consecutive launches count as kernel time: an upper bound)."""
     import torch
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(launches)]
-    for a, b in evs:
-        a.record(stream)
-        sim.step(depth)
-        b.record(stream)
+    sim.step(depth)  # untimed
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    sim.step(depth * launches)
+    b.record(stream)
     torch.cuda.synchronize()
-    return sum(a.elapsed_time(b) for a, b in evs) / launches / 1e3
+    return a.elapsed_time(b) / launches / 1e3
+
+
+def memory_ceiling(wl, depth: int, band: int, kernel_s: float, has_mask: bool) -> dict:
+    """The pass's own memory accesses without its arithmetic: the streaming
+    reference kernel with the step kernel's shape (full-width bands of `band`
+    rows, `depth` halo rows on each side, seven planes + mask read, seven
+    planes written), and plain 16-byte streaming of 1 GiB, both timed here.
+    `frac_of_pass_copy` compares the step kernel's time with the reference
+    kernel's for the same accesses."""
+    from paper_1208_2428_amd import calib
+    wd = wl.width // 64
+    ref = calib.pass_rate("copy", wd, wl.height, band, depth, has_mask, launches=50)
+    flat = calib.flat_rate("copy", 1 << 30, launches=20)
+    moved = calib.pass_bytes("copy", wd, wl.height, band, depth, has_mask)
+    log(f"bench: pass-shaped copy {ref['gbs']:.0f} GB/s ({ref['us']:.1f} us), flat copy "
+        f"{flat['gbs']:.0f} GB/s; the step kernel moves {moved / kernel_s / 1e9:.0f} GB/s")
+    return {"pass_copy_gbs": ref["gbs"], "pass_copy_us": ref["us"], "pass_bytes": moved,
+            "flat_copy_gbs": flat["gbs"], "kernel_gbs_of_pass_bytes": moved / kernel_s / 1e9,
+            "frac_of_pass_copy": ref["us"] / (kernel_s * 1e6),
+            "algorithmic_frac_of_flat_copy": PLANE_BITS * wl.width * wl.height / 8 / kernel_s
+            / 1e9 / flat["gbs"]}
 
 
 def small_config(name: str, min_seconds: float):
@@ -399,6 +421,8 @@ def main() -> int:
                     help="skip the throughput / roofline sweep over depths 1..5")
     ap.add_argument("--sweep-seconds", type=float, default=0.1,
                     help="HIP-event time covered at each depth of the sweep")
+    ap.add_argument("--no-ceiling", action="store_true",
+                    help="skip the measured memory ceilings (streaming reference kernels)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 256^2 torus and 4096^2 channel workloads")
     args = ap.parse_args()
@@ -449,6 +473,7 @@ def main() -> int:
     launch_s = launch_seconds(sim, stream, depth, args.launches)
     bytes_per_launch = PLANE_BITS * nodes / 8  # 14/k bits per node-step, k steps per launch
     achieved = bytes_per_launch / launch_s / 1e9
+    band = sim.band
     sim.close()
     traffic = recorded_traffic(wl.name, depth)
     valu = recorded_valu(wl.name, depth)
@@ -479,6 +504,8 @@ def main() -> int:
                      "kernel_us": launch_s * 1e6, "launches_timed": args.launches,
                      "bytes_per_launch": bytes_per_launch},
     }
+    if not args.no_ceiling:
+        out["roofline"]["ceiling"] = memory_ceiling(wl, depth, band, launch_s, mask is not None)
     if valu is not None:
         # the same launch against the VALU issue limit (wave64 instructions;
         # integer multiplies issue at the bit-operation rate on this GPU)

@@ -149,6 +149,8 @@ int fhp_get_depth(const fhp_sim *s, uint32_t *k);
  * K halo rows above and below it.  Results do not depend on it.  FHP_E_INVAL
  * above the lattice height. */
 int fhp_set_band(fhp_sim *s, uint32_t rows);
+/* The band height fhp_step uses: the one set, or the default it resolves to. */
+int fhp_get_band(const fhp_sim *s, uint32_t *rows);
 
 /* Advances n steps (Sec. 2: motion then scattering, each step).  Asynchronous:
  * enqueued on the handle's stream.  FHP_E_STATE if t + n would reach 2^24. */

@@ -57,6 +57,7 @@ _SIGNATURES = {
     "fhp_set_depth": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
     "fhp_get_depth": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
     "fhp_set_band": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32]),
+    "fhp_get_band": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32)]),
     "fhp_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "fhp_observe": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_void_p,
                                    ctypes.c_size_t]),
@@ -109,7 +110,15 @@ _SIGNATURES = {
     "fhp_step_noalloc": (ctypes.c_int, [ctypes.POINTER(Params), ctypes.c_void_p, ctypes.c_void_p,
                                         ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
                                         ctypes.c_uint32, ctypes.c_void_p]),
+    "fhp_calib_pass": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]),
+    "fhp_calib_flat": (ctypes.c_int, [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                      ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
+                                      ctypes.c_void_p]),
 }
+
+CALIB_COPY, CALIB_READ, CALIB_WRITE = 0, 1, 2
 
 NOALLOC_MAX_STATE_BYTES = 64 << 20
 

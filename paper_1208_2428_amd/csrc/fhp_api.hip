@@ -243,6 +243,12 @@ int fhp_set_band(fhp_sim* s, uint32_t rows) {
     return FHP_OK;
 }
 
+int fhp_get_band(const fhp_sim* s, uint32_t* rows) {
+    if (!s || !rows) return fail(FHP_E_INVAL, "NULL argument");
+    *rows = s->band ? s->band : default_band(s->L.H, s->L.wd, s->simds);
+    return FHP_OK;
+}
+
 int fhp_get_depth(const fhp_sim* s, uint32_t* k) {
     if (!s || !k) return fail(FHP_E_INVAL, "NULL argument");
     *k = s->depth;

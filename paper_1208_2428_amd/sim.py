@@ -76,6 +76,13 @@ class Sim:
         B.check(self._lib.fhp_set_band(self._handle(), int(rows)))
 
     @property
+    def band(self) -> int:
+        """Rows per band of the blocked kernel (the default resolved)."""
+        v = ctypes.c_uint32(0)
+        B.check(self._lib.fhp_get_band(self._handle(), ctypes.byref(v)))
+        return int(v.value)
+
+    @property
     def t(self) -> int:
         v = ctypes.c_uint64()
         B.check(self._lib.fhp_time(self._handle(), ctypes.byref(v)))

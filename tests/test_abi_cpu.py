@@ -146,3 +146,30 @@ def test_step_noalloc_argument_checks(lib):
     mask = np.zeros((8, 128), np.uint8)
     p, keep = B.make_params(128, 8, solid=mask)
     assert lib.fhp_step_noalloc(ctypes.byref(p), x, y, None, 0, 5, 0, None) == B.E_INVAL
+
+
+def test_calibration_argument_checks(lib):
+    """The streaming reference kernels reject what they cannot run before any
+    launch (the pointers below are never dereferenced)."""
+    x, y = ctypes.c_void_p(1 << 20), ctypes.c_void_p(2 << 20)
+    ok = dict(wd=256, H=64, ps=256 * 64, band=32, halo=5)
+
+    def cp(mode=B.CALIB_COPY, src=x, dst=y, **kw):
+        a = {**ok, **kw}
+        return lib.fhp_calib_pass(mode, src, dst, None, a["wd"], a["H"], a["ps"], a["band"],
+                                  a["halo"], None)
+
+    assert cp(mode=3) == B.E_INVAL
+    assert cp(wd=0) == B.E_INVAL and cp(wd=513) == B.E_INVAL
+    assert cp(H=0) == B.E_INVAL and cp(band=0) == B.E_INVAL
+    assert cp(halo=9) == B.E_INVAL
+    assert cp(ps=256 * 64 - 1) == B.E_INVAL
+    assert cp(ps=1 << 27) == B.E_INVAL  # seven planes of 1 GiB
+    assert cp(src=None) == B.E_INVAL and cp(dst=None) == B.E_INVAL
+    n = ctypes.c_uint32(0)
+    assert lib.fhp_calib_flat(B.CALIB_COPY, x, y, 24, 4, ctypes.byref(n), None) == B.E_INVAL
+    assert lib.fhp_calib_flat(B.CALIB_COPY, x, y, 0, 4, ctypes.byref(n), None) == B.E_INVAL
+    assert lib.fhp_calib_flat(B.CALIB_COPY, ctypes.c_void_p((1 << 20) + 8), y, 1 << 20, 4,
+                              ctypes.byref(n), None) == B.E_INVAL
+    assert lib.fhp_calib_flat(B.CALIB_READ, None, y, 1 << 20, 4, ctypes.byref(n), None) == B.E_INVAL
+    assert lib.fhp_calib_flat(5, x, y, 1 << 20, 4, ctypes.byref(n), None) == B.E_INVAL
