@@ -70,3 +70,58 @@ def test_darcy_flow_through_obstacles_is_linear_in_the_force():
     print("darcy", means, flush=True)
     assert means[0] > 0 and means[1] > 0
     assert 1.7 < means[1] / means[0] < 2.3
+
+
+def test_permeability_chain_matches_oracle_states():
+    """Superficial velocity, body force and the channel viscosity computed
+    from the GPU's observables equal the ones computed from the oracle's
+    states, float for float (a small obstacle field and a small channel)."""
+    W, H, f, seed = 256, 96, 3e-3, 17
+    mask = WL.porous_mask(W, H, seed=8, rmin=3, rmax=6, frac=0.15)
+    s = Sim(W, H, seed=seed, fill=0.3, force_rate=f, solid=mask)
+    got = flow.darcy_sums(s, steps=300, every=50, start=100)
+    s.close()
+    st = oracle.init(W, H, seed, 0.3, mask=mask)
+    st, _ = oracle.run(st, 0, 100, seed, f, threads=THREADS)
+    qs, gs = [], []
+    for k in range(6):
+        st, _ = oracle.run(st, 100 + 50 * k, 50, seed, f, threads=THREADS)
+        glob = oracle.observe_global(st)
+        qs.append(flow.superficial_velocity(glob, W * H))
+        gs.append(flow.body_force(glob, W * H, f))
+    assert got["q"] == float(np.mean(qs)) and got["g"] == float(np.mean(gs))
+
+    W, H = 512, 34
+    s = Sim(W, H, seed=seed, fill=0.3, force_rate=f, walls=True)
+    nu = flow.channel_viscosity(s, steps=400, every=50, start=200)
+    s.close()
+    st = oracle.init(W, H, seed, 0.3, walls=True)
+    st, _ = oracle.run(st, 0, 200, seed, f, threads=THREADS)
+    acc, gs = np.zeros(H), []
+    for k in range(8):
+        st, _ = oracle.run(st, 200 + 50 * k, 50, seed, f, threads=THREADS)
+        acc += flow.row_velocity(oracle.observe_rows(st))
+        gs.append(flow.body_force(oracle.observe_global(st), W * H, f))
+    np.testing.assert_equal(nu["nu"], flow.viscosity(acc / 8, float(np.mean(gs))))
+
+
+def test_permeability_scales_with_obstacle_size_squared():
+    """Darcy permeability of random disks at one solid fraction (20%) with
+    every length doubled: about four times larger (k ~ R^2 at fixed
+    porosity), measured with the full chain (channel viscosity at the same
+    density, body force, superficial velocity)."""
+    W = H = 1024
+    f = 1e-3
+    ch = Sim(2048, 66, seed=3, fill=0.3, force_rate=f, walls=True)
+    nu = flow.channel_viscosity(ch, steps=20000, every=200, start=20000)["nu"]
+    ch.close()
+    ks = []
+    for seed, (rmin, rmax) in ((51, (4, 8)), (52, (8, 16))):
+        mask = WL.porous_mask(W, H, seed=seed, rmin=rmin, rmax=rmax, frac=0.2)
+        s = Sim(W, H, seed=seed, fill=0.3, force_rate=f, solid=mask)
+        d = flow.darcy_sums(s, steps=6000, every=100, start=4000)
+        s.close()
+        ks.append(flow.permeability(d["q"], d["g"], nu))
+    print("viscosity", nu, "permeabilities", ks, flush=True)
+    assert 0.05 < nu < 2.0
+    assert ks[0] > 0 and 3.0 < ks[1] / ks[0] < 5.5
