@@ -157,19 +157,21 @@ def recorded_valu(name: str, depth: int):
     return insts
 
 
-def depth_sweep(wl, mask, min_seconds: float):
+def depth_sweep(wl, mask, min_seconds: float, last: int | None = None):
     """Throughput and HBM roofline fraction of the single-lattice kernel at
     every depth, each timed with HIP events over at least `min_seconds` (the
-    fraction of 14/K bits per node-step falls with K by construction)."""
+    fraction of 14/K bits per node-step falls with K by construction); depth
+    `last` is measured last."""
     from paper_1208_2428_amd import _binding as B
+    ks = [k for k in range(1, B.MAX_DEPTH + 1) if k != last] + ([last] if last else [])
     out = []
-    for k in range(1, B.MAX_DEPTH + 1):
+    for k in ks:
         v, n = plain_rate(wl, mask, k, min_seconds)
         frac = v * PLANE_BITS / k / 8 / 1e9 / HBM_PEAK_GBS
         out.append({"depth": k, "value": v, "frac": frac, "steps": n})
         log(f"bench: depth {k}: {v:.3e} node-updates/s over {n} steps, "
             f"{frac:.3f} of the HBM roofline")
-    return out
+    return sorted(out, key=lambda d: d["depth"])
 
 
 def plain_rate(wl, mask, depth: int, min_seconds: float = 0.1):
@@ -351,6 +353,40 @@ def memory_ceiling(wl, depth: int, band: int, has_mask: bool) -> dict:
             "flat_copy_gbs": flat["gbs"]}
 
 
+def flow_leg(wl, mask) -> dict:
+    """Darcy permeability of the workload's obstacle geometry (paper Sec. 2:
+    forcing as a body force driving the flow), k = nu q / g.  nu: a forced
+    channel of 2048 x 130 nodes at the workload's density (plane Poiseuille
+    flow, u'' = -g / nu), 25,000 steps to settle, then profiles every 200
+    steps for 40,000.  q, g: the workload's lattice and mask at a force rate
+    low enough for linear (Darcy) flow, 60,000 steps to settle (the flow's
+    relaxation time k / nu is about 10^4 steps), then global sums every 500
+    steps for 20,000.  Both runs are GPU runs of the library; flow.py only
+    averages and fits the sums."""
+    from paper_1208_2428_amd import Sim, flow
+    t0 = time.perf_counter()
+    ch = Sim(2048, 130, seed=11, fill=wl.fill, force_rate=5e-5, walls=True)
+    v = flow.channel_viscosity(ch, steps=40000, every=200, start=25000)
+    ch.close()
+    f_por = 2e-5
+    sim = Sim(wl.width, wl.height, seed=wl.seed, fill=wl.fill, force_rate=f_por,
+              walls=wl.walls, solid=mask)
+    d = flow.darcy_sums(sim, steps=20000, every=500, start=60000)
+    sim.close()
+    k = flow.permeability(d["q"], d["g"], v["nu"])
+    porosity = 1.0 - (float(mask.mean()) if mask is not None else 0.0)
+    log(f"bench: viscosity {v['nu']:.4f} (channel fit R^2 {v['r2']:.4f}), permeability "
+        f"{k:.1f} lattice constants^2 (q {d['q']:.4f}, g {d['g']:.3e}); "
+        f"{time.perf_counter() - t0:.1f} s")
+    return {"permeability": k, "unit": "lattice constants^2", "porosity": porosity,
+            "superficial_velocity": d["q"], "body_force": d["g"], "force_rate": f_por,
+            "steps": 80000, "viscosity": v["nu"],
+            "viscosity_channel": {"width": 2048, "height": 130, "force_rate": 5e-5,
+                                  "body_force": v["g"], "fit_r2": v["r2"], "peak": v["peak"],
+                                  "steps": 65000},
+            "fill": wl.fill}
+
+
 def small_config(name: str, min_seconds: float):
     """A smaller named workload run in full from its initial state (digest
     against the oracle's at its last step), then timed with HIP events over
@@ -422,6 +458,8 @@ def main() -> int:
                     help="HIP-event time covered at each depth of the sweep")
     ap.add_argument("--no-ceiling", action="store_true",
                     help="skip the measured memory ceilings (streaming reference kernels)")
+    ap.add_argument("--no-flow", action="store_true",
+                    help="skip the permeability of the workload's geometry")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 256^2 torus and 4096^2 channel workloads")
     args = ap.parse_args()
@@ -442,32 +480,29 @@ def main() -> int:
     mask = wl.mask()
     solid_frac = float(mask.mean()) if mask is not None else 0.0
 
-    # The reference measurements run first: on this device the first few
-    # hundred launches after an idle spell run up to 35% slower than in
-    # sustained operation (the kernel trace goes 134 -> 170 -> 124 us per
-    # launch over about 40 ms), so the timed steps below follow a second or
-    # two of other GPU work, like the steps of a long run.
-    probe = Sim(**wl.params(), solid=mask, depth=args.depth, band=args.band)
-    depth, band = probe.depth, probe.band
-    probe.close()
-    del probe
+    # The device raises its clock over a few tens of milliseconds of sustained
+    # load: right after an idle spell (even the few milliseconds of setting up
+    # a lattice) the step kernel's launches take up to 10% longer (the SQ
+    # counters show 2.04 GHz rising to 2.27 GHz over the first launches).  So
+    # both lattices are set up first, the reference measurements follow, and
+    # the warm-up and the timed steps come right after them, as in the middle
+    # of a long run.
+    warm = Sim(**wl.params(), solid=mask, depth=args.depth, band=args.band)
+    depth, band = warm.depth, warm.band
+    sim = Sim(**wl.params(), solid=mask, depth=depth, band=args.band)
     ceiling = None
     if not args.no_ceiling:
         ceiling = memory_ceiling(wl, depth, band, has_mask=mask is not None)
     plain = {}
     sweep = None
     if not args.no_depth_sweep:
-        sweep = depth_sweep(wl, mask, args.sweep_seconds)
+        sweep = depth_sweep(wl, mask, args.sweep_seconds, last=depth)
         plain = {d["depth"]: d["value"] for d in sweep}
 
-    warm = Sim(**wl.params(), solid=mask, depth=depth, band=args.band)
     log(f"bench: warmup {args.warmup} steps at depth {depth}")
     warm.step(args.warmup)
     warm.sync()
-    warm.close()
-    del warm
 
-    sim = Sim(**wl.params(), solid=mask, depth=depth, band=args.band)
     nodes = wl.width * wl.height
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -490,6 +525,8 @@ def main() -> int:
     bytes_per_launch = PLANE_BITS * nodes / 8  # 14/k bits per node-step, k steps per launch
     achieved = bytes_per_launch / launch_s / 1e9
     sim.close()
+    warm.close()
+    del sim, warm
     traffic = recorded_traffic(wl.name, depth)
     valu = recorded_valu(wl.name, depth)
     log(f"bench: {args.launches} launches of depth {depth}: {launch_s * 1e6:.1f} us each, "
@@ -549,6 +586,8 @@ def main() -> int:
         out["served"] = served_leg(args, plain_at, depth)
     if not args.no_rules:
         out["rule_sets"] = rules_leg(args, wl, mask, plain_at)
+    if not args.no_flow:
+        out["flow"] = flow_leg(wl, mask)
     if not args.no_cpu_baseline:
         log(f"bench: timing the CPU oracle for ~{args.cpu_seconds:.0f} s")
         out["cpu_baseline"] = cpu_baseline(wl, mask, args.cpu_seconds)

@@ -54,7 +54,9 @@ namespace {
 
 constexpr size_t kStepkLdsBytes = 2 * 4 * kMaxBlockedWords * sizeof(uint32_t);
 
-template <int K, bool FORCE, bool MASK, int RULES, bool WIDE>
+// ONE_WAVE: rows of exactly 64 words, one wave per band; the carries move
+// between lanes by DPP (gather_wave) instead of through LDS.
+template <int K, bool FORCE, bool MASK, int RULES, bool WIDE, bool ONE_WAVE = false>
 __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
                                                 uint64_t* __restrict__ out,
                                                 const uint64_t* __restrict__ S, StepkArgs a) {
@@ -141,9 +143,14 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
             }
         };
         constexpr bool odd0 = ((PAR + K) & 1) != 0;  // y0 even: parity of y
-        publish<odd0>(xch, slot, kMaxBlockedWords, lane, X);
-        if (FULL || i >= 2) hashes(1);
-        gather<odd0>(xch, slot, kMaxBlockedWords, wl, wr, X);
+        if constexpr (ONE_WAVE) {
+            if (FULL || i >= 2) hashes(1);
+            gather_wave<odd0>(X);
+        } else {
+            publish<odd0>(xch, slot, kMaxBlockedWords, lane, X);
+            if (FULL || i >= 2) hashes(1);
+            gather<odd0>(xch, slot, kMaxBlockedWords, wl, wr, X);
+        }
         bool have = true;  // X holds a new row of level l-1
         static_for<1, K>([&](auto lc) __attribute__((always_inline)) {
             constexpr int l = decltype(lc)::value;
@@ -165,9 +172,14 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
             Y.s = sw;
             push(lc, X);
             if (l < K) {
-                publish<odd>(xch, slot, kMaxBlockedWords, lane, Y);
-                if (FULL || i >= 2 * (l + 1)) hashes(l + 1);
-                gather<odd>(xch, slot, kMaxBlockedWords, wl, wr, Y);
+                if constexpr (ONE_WAVE) {
+                    if (FULL || i >= 2 * (l + 1)) hashes(l + 1);
+                    gather_wave<odd>(Y);
+                } else {
+                    publish<odd>(xch, slot, kMaxBlockedWords, lane, Y);
+                    if (FULL || i >= 2 * (l + 1)) hashes(l + 1);
+                    gather<odd>(xch, slot, kMaxBlockedWords, wl, wr, Y);
+                }
                 X = Y;
             } else if (valid) {
                 const uint32_t off = offset(rho);
@@ -203,47 +215,54 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
     }
 }
 
-template <bool WIDE, int K, bool FORCE, bool MASK, int RULES = kRulesFHP2>
+template <bool WIDE, int K, bool FORCE, bool MASK, int RULES = kRulesFHP2, bool ONE_WAVE = false>
 hipError_t launch_k(const uint64_t* in, uint64_t* out, const Lattice& L, const StepkArgs& a,
                     hipStream_t st) {
     const uint32_t nt = (L.wd + 63) / 64 * 64;
     const uint32_t bands = (L.H + a.T - 1) / a.T;
-    hipLaunchKernelGGL((k_stepk<K, FORCE, MASK, RULES, WIDE>), dim3(bands), dim3(nt), kStepkLdsBytes,
-                       st, in, out, L.S, a);
+    if constexpr (ONE_WAVE) {
+        if (L.wd != 64) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_stepk<K, FORCE, MASK, RULES, WIDE, true>), dim3(bands), dim3(64), 0,
+                           st, in, out, L.S, a);
+    } else {
+        hipLaunchKernelGGL((k_stepk<K, FORCE, MASK, RULES, WIDE>), dim3(bands), dim3(nt),
+                           kStepkLdsBytes, st, in, out, L.S, a);
+    }
     return hipGetLastError();
 }
 
 // FHP-II has a kernel for every combination of forcing and obstacles; the
 // other rule sets use the forcing variant (a zero rate draws no coin).
-template <bool WIDE, int K>
+template <bool WIDE, int K, bool OW = false>
 hipError_t launch_k2(const uint64_t* in, uint64_t* out, const Lattice& L, const StepkArgs& a,
                      uint32_t rules, hipStream_t st) {
     const bool force = a.thr_force != 0, mask = L.S != nullptr;
     if (rules == kRulesFHP1)
-        return mask ? launch_k<WIDE, K, true, true, kRulesFHP1>(in, out, L, a, st)
-                    : launch_k<WIDE, K, true, false, kRulesFHP1>(in, out, L, a, st);
+        return mask ? launch_k<WIDE, K, true, true, kRulesFHP1, OW>(in, out, L, a, st)
+                    : launch_k<WIDE, K, true, false, kRulesFHP1, OW>(in, out, L, a, st);
     if (rules == kRulesFHP3) {
         if constexpr (K <= kMaxDepthFHP3)
-            return mask ? launch_k<WIDE, K, true, true, kRulesFHP3>(in, out, L, a, st)
-                        : launch_k<WIDE, K, true, false, kRulesFHP3>(in, out, L, a, st);
+            return mask ? launch_k<WIDE, K, true, true, kRulesFHP3, OW>(in, out, L, a, st)
+                        : launch_k<WIDE, K, true, false, kRulesFHP3, OW>(in, out, L, a, st);
         return hipErrorInvalidValue;
     }
-    if (force) return mask ? launch_k<WIDE, K, true, true>(in, out, L, a, st)
-                           : launch_k<WIDE, K, true, false>(in, out, L, a, st);
-    return mask ? launch_k<WIDE, K, false, true>(in, out, L, a, st)
-                : launch_k<WIDE, K, false, false>(in, out, L, a, st);
+    if (force) return mask ? launch_k<WIDE, K, true, true, kRulesFHP2, OW>(in, out, L, a, st)
+                           : launch_k<WIDE, K, true, false, kRulesFHP2, OW>(in, out, L, a, st);
+    return mask ? launch_k<WIDE, K, false, true, kRulesFHP2, OW>(in, out, L, a, st)
+                : launch_k<WIDE, K, false, false, kRulesFHP2, OW>(in, out, L, a, st);
 }
 
-// Launches the pass of depth K for buffers of the given width class.
-template <bool WIDE>
+// Launches the pass of depth K for buffers of the given width class
+// (OW: the one-wave kernel for rows of 64 words).
+template <bool WIDE, bool OW = false>
 hipError_t launch_depth(uint32_t K, const uint64_t* in, uint64_t* out, const Lattice& L, const StepkArgs& a,
                         uint32_t rules, hipStream_t st) {
     switch (K) {
-        case 1: return launch_k2<WIDE, 1>(in, out, L, a, rules, st);
-        case 2: return launch_k2<WIDE, 2>(in, out, L, a, rules, st);
-        case 3: return launch_k2<WIDE, 3>(in, out, L, a, rules, st);
-        case 4: return launch_k2<WIDE, 4>(in, out, L, a, rules, st);
-        case 5: return launch_k2<WIDE, 5>(in, out, L, a, rules, st);
+        case 1: return launch_k2<WIDE, 1, OW>(in, out, L, a, rules, st);
+        case 2: return launch_k2<WIDE, 2, OW>(in, out, L, a, rules, st);
+        case 3: return launch_k2<WIDE, 3, OW>(in, out, L, a, rules, st);
+        case 4: return launch_k2<WIDE, 4, OW>(in, out, L, a, rules, st);
+        case 5: return launch_k2<WIDE, 5, OW>(in, out, L, a, rules, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -253,6 +272,9 @@ hipError_t launch_depth(uint32_t K, const uint64_t* in, uint64_t* out, const Lat
 // The pass for buffers of seven planes above 4 GiB (fhp_stepk_wide.hip, its
 // own translation unit so that the two halves compile in parallel).
 hipError_t launch_stepk_wide(uint32_t K, const uint64_t* in, uint64_t* out, const Lattice& L,
+                             const StepkArgs& a, uint32_t rules, hipStream_t st);
+// The pass for rows of exactly 64 words, one wave per band (fhp_stepk_wave.hip).
+hipError_t launch_stepk_wave(uint32_t K, const uint64_t* in, uint64_t* out, const Lattice& L,
                              const StepkArgs& a, uint32_t rules, hipStream_t st);
 
 }  // namespace fhp

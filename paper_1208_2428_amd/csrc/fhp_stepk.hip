@@ -20,6 +20,7 @@ hipError_t launch_stepk(uint32_t K, const uint64_t* in, uint64_t* out, const Lat
     a.chi_and = (D.chir_mode == FHP_CHIR_HASH) ? ~0u : 0u;
     a.chi_or = (D.chir_mode == FHP_CHIR_ONE) ? ~0u : 0u;
     if (planes_wide(L.ps)) return launch_stepk_wide(K, in, out, L, a, D.rules, st);
+    if (L.wd == 64) return launch_stepk_wave(K, in, out, L, a, D.rules, st);
     return launch_depth<false>(K, in, out, L, a, D.rules, st);
 }
 

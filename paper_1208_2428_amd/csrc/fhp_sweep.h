@@ -167,6 +167,27 @@ __device__ __forceinline__ void gather(const uint32_t* xch, uint32_t& slot, uint
     slot ^= 1;
 }
 
+// Rows held by a single wave (64 words, lane = word): the neighbour halves come
+// from the adjacent lanes through DPP wave rotations, with no LDS and no
+// barrier.  wave_ror:1 hands each lane the value of the lane below it (lane 0
+// gets lane 63's: the periodic wrap of a 64-word row), wave_rol:1 the value
+// of the lane above it.
+__device__ __forceinline__ uint32_t from_left_lane(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x13C, 0xf, 0xf, false);
+}
+__device__ __forceinline__ uint32_t from_right_lane(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x134, 0xf, 0xf, false);
+}
+
+// gather() for a row held by one wave.
+template <bool ODD>
+__device__ __forceinline__ void gather_wave(Row& x) {
+    x.c[0] = ODD ? from_left_lane(hi32(x.p[1])) : from_right_lane(lo32(x.p[0]));
+    x.c[1] = from_left_lane(hi32(x.p[2]));
+    x.c[2] = from_right_lane(lo32(x.p[5]));
+    x.c[3] = ODD ? from_left_lane(hi32(x.p[3])) : from_right_lane(lo32(x.p[4]));
+}
+
 template <bool ODD>
 __device__ __forceinline__ void exchange(uint32_t* xch, uint32_t& slot, uint32_t stride, uint32_t lane,
                                          uint32_t wl, uint32_t wr, Row& x) {

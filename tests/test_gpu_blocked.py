@@ -107,3 +107,30 @@ def test_state_buffer_above_4gib():
         del s
         torch.cuda.empty_cache()
     assert got[5] == got[1]
+
+
+@pytest.mark.parametrize("band", [2, 4, 6, 12, 40])
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("rules", [0, 1, 2])
+def test_one_wave_rows(band, K, rules):
+    """Rows of 64 words run the one-wave pass (carries between lanes by DPP,
+    the periodic wrap from lane 63 to lane 0): every pass equals the oracle,
+    for every band height, depth and rule set, with walls, obstacles,
+    particles on solid nodes and forcing."""
+    W, H = 4096, 40
+    say("one-wave", band, K, rules)
+    rng = np.random.default_rng(1000 * band + 10 * K + rules)
+    st = make_state(rng, W, H, "solid-particles")
+    st[0] |= 0x80   # the wall rows, as the state bytes of a lattice with walls hold them
+    st[-1] |= 0x80
+    f = 1.0 / 70
+    s = Sim(W, H, seed=77, force_rate=f, walls=True, depth=K, band=band, rules=rules)
+    s.set_state(st, t=3)
+    ref, t = st.copy(), 3
+    for n in (K, 2 * K + 1, 3):
+        s.step(n)
+        ref, _ = oracle.run(ref, t, n, 77, f, threads=THREADS, rules=rules)
+        t += n
+        np.testing.assert_array_equal(s.get_state(), ref, err_msg=f"t={t}")
+    assert s.digest() == oracle.digest(ref)
+    s.close()
