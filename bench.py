@@ -499,6 +499,15 @@ def main() -> int:
         sweep = depth_sweep(wl, mask, args.sweep_seconds, last=depth)
         plain = {d["depth"]: d["value"] for d in sweep}
 
+    # Per-launch duration of the step kernel (events on the kernel's stream),
+    # on the warm-up lattice: the same kernel, lattice and mask as the timed
+    # one, so the timed lattice still starts from t = 0.
+    launch_s = launch_seconds(warm, stream, depth, args.launches)
+    bytes_per_launch = PLANE_BITS * wl.width * wl.height / 8  # 14/k bits per node-step, k steps per launch
+    achieved = bytes_per_launch / launch_s / 1e9
+    log(f"bench: {args.launches} launches of depth {depth}: {launch_s * 1e6:.1f} us each, "
+        f"{achieved / HBM_PEAK_GBS:.3f} of the HBM roofline")
+
     log(f"bench: warmup {args.warmup} steps at depth {depth}")
     warm.step(args.warmup)
     warm.sync()
@@ -520,17 +529,11 @@ def main() -> int:
     parity = None if ref is None else (digest == ref)
     log(f"bench: digest at t={args.steps}: {digest:016x}, oracle {'n/a' if ref is None else f'{ref:016x}'}")
 
-    # Per-launch duration of the step kernel, with events on the kernel's stream.
-    launch_s = launch_seconds(sim, stream, depth, args.launches)
-    bytes_per_launch = PLANE_BITS * nodes / 8  # 14/k bits per node-step, k steps per launch
-    achieved = bytes_per_launch / launch_s / 1e9
     sim.close()
     warm.close()
     del sim, warm
     traffic = recorded_traffic(wl.name, depth)
     valu = recorded_valu(wl.name, depth)
-    log(f"bench: {args.launches} launches of depth {depth}: {launch_s * 1e6:.1f} us each, "
-        f"{achieved / HBM_PEAK_GBS:.3f} of the HBM roofline")
 
     value = nodes * args.steps / wall
     out = {

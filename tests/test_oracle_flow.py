@@ -79,7 +79,7 @@ def test_body_force_matches_counted_swaps():
         swaps += s
     mass = oracle.observe_global(st)["mass"]
     counted = 2.0 * swaps / t / mass
-    # ~5,500 swaps: 1.4% statistical error
+    # ~4,850 swaps: 1.4% statistical error
     assert abs(np.mean(gs) / counted - 1.0) < 0.06, (np.mean(gs), counted)
 
 
