@@ -296,6 +296,11 @@ def served_leg(args, plain_at, depth):
     reqs80 = WL.request_stream(n=n80, rate=rate80, seed=6)
     at80 = srv.run(reqs80, realtime=True, log=log)
     log(f"bench: at {rate80:.0f} req/s: p50 {at80['p50_ms']:.0f} ms, p99 {at80['p99_ms']:.0f} ms")
+    for name, r in (("overloaded", hot), ("at 80%", at80)):
+        log(f"bench: {name}: queue p50/p99 {r['queue_p50_ms']:.0f}/{r['queue_p99_ms']:.0f} ms, "
+            f"in pool {r['pool_p50_ms']:.0f}/{r['pool_p99_ms']:.0f} ms; latency p99 by work third "
+            + ", ".join(f"{t['latency_p99_ms']:.0f}" for t in r["by_work"])
+            + f" ms; corr(log latency, log work) {r.get('log_latency_log_work_corr', 0):.2f}")
     srv.close()
     same = 0
     for i in sample:
@@ -306,7 +311,8 @@ def served_leg(args, plain_at, depth):
         sim.close()
     log(f"bench: {same}/{len(sample)} sampled served jobs equal to the same job run alone")
     keys = ("requests", "completed", "seconds", "value", "p50_ms", "p99_ms", "mean_ms",
-            "max_queue", "max_resident", "ticks")
+            "max_queue", "max_resident", "ticks", "queue_p50_ms", "queue_p99_ms", "pool_p50_ms",
+            "pool_p99_ms", "by_work", "log_latency_log_work_corr")
     return {"value": hot["value"], "unit": "node-updates/s", "depth": depth,
             "plain_value_same_depth": plain, "ratio_vs_plain": hot["value"] / plain,
             "timing": "wall clock from the first arrival to the last result on the host",

@@ -7,7 +7,9 @@ the pool whenever a slot and arena memory (the HBM budget) are free; every
 resident job advances with each tick (one batch-kernel launch per pass over
 all resident jobs); a finished job's 16 x 16 block sums of density and
 momentum are copied to the host and its memory is freed for the queue.
-Latency is measured from a request's arrival to its result on the host.
+Latency is measured from a request's arrival to its result on the host, and
+split into the wait in the queue (arrival to admission) and the time in the
+pool (admission to result); both are reported by job size (node updates).
 """
 from __future__ import annotations
 
@@ -57,6 +59,8 @@ class Server:
         collecting: dict[int, np.ndarray] = {}
         in_flight: deque = deque()
         lat, results = [], {}
+        admitted_at: dict[int, float] = {}
+        waits, services, works = [], [], []
         node_updates = 0
         ticks = max_queue = max_active = 0
         while pending or queue or inflight:
@@ -75,6 +79,7 @@ class Server:
                     break
                 queue.popleft()
                 inflight[slot] = (idx, r)
+                admitted_at[slot] = time.perf_counter() - start
             max_active = max(max_active, len(inflight))
             if not inflight:
                 if pending:
@@ -99,7 +104,12 @@ class Server:
                 blocks = collecting.pop(slot)
                 idx, r = inflight.pop(slot)
                 t_done = time.perf_counter() - start
-                lat.append(t_done - (r.arrival if realtime else 0.0))
+                t_arr = r.arrival if realtime else 0.0
+                t_adm = admitted_at.pop(slot)
+                lat.append(t_done - t_arr)
+                waits.append(max(0.0, t_adm - t_arr))
+                services.append(t_done - t_adm)
+                works.append(r.side * r.side * r.steps)
                 node_updates += r.side * r.side * r.steps
                 if keep_results is not None and idx in keep_results:
                     results[idx] = blocks.copy()
@@ -117,12 +127,38 @@ class Server:
                "p50_ms": float(np.percentile(lat_ms, 50)) if len(lat) else None,
                "p99_ms": float(np.percentile(lat_ms, 99)) if len(lat) else None,
                "mean_ms": float(lat_ms.mean()) if len(lat) else None}
+        if len(lat):
+            out.update(latency_breakdown(np.array(waits), np.array(services), np.array(works)))
         if keep_results is not None:
             out["results"] = results
         return out
 
     def close(self) -> None:
         self.pool.close()
+
+
+def latency_breakdown(waits: np.ndarray, services: np.ndarray, works: np.ndarray) -> dict:
+    """Where the latency goes: p50/p99 of the queue wait and of the time in
+    the pool, overall and for the jobs in each third of the work (node
+    updates), and the correlation of latency with work (logarithms)."""
+    def pct(a, q):
+        return float(np.percentile(a * 1e3, q)) if len(a) else None
+    lat = waits + services
+    out = {"queue_p50_ms": pct(waits, 50), "queue_p99_ms": pct(waits, 99),
+           "pool_p50_ms": pct(services, 50), "pool_p99_ms": pct(services, 99)}
+    edges = np.quantile(works, [1 / 3, 2 / 3])
+    thirds = []
+    for name, sel in (("small", works <= edges[0]),
+                      ("medium", (works > edges[0]) & (works <= edges[1])),
+                      ("large", works > edges[1])):
+        thirds.append({"jobs": name, "count": int(sel.sum()),
+                       "work_max": float(works[sel].max()) if sel.any() else None,
+                       "latency_p50_ms": pct(lat[sel], 50), "latency_p99_ms": pct(lat[sel], 99),
+                       "queue_p50_ms": pct(waits[sel], 50), "pool_p50_ms": pct(services[sel], 50)})
+    out["by_work"] = thirds
+    if len(lat) > 2:
+        out["log_latency_log_work_corr"] = float(np.corrcoef(np.log(works), np.log(lat))[0, 1])
+    return out
 
 
 def offered_load(requests: list[WL.Request]) -> float:
