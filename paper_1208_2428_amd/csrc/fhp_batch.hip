@@ -221,6 +221,8 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
         };
         Row nxt;
         load(-K, nxt);
+        constexpr bool kPairs = RULES != kRulesFHP3 && (K <= 4 || (!FORCE && !MASK));
+        uint64_t held[7];  // the last even output row, stored with the next one (kPairs)
 
         auto body = [&](int i, auto full_c, auto par_c) __attribute__((always_inline)) {
             constexpr bool FULL = decltype(full_c)::value;
@@ -275,9 +277,30 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
                     exchange<odd>(xch, slot, nt, lane, wl, wr, Y);
                     X = Y;
                 } else if (active) {
-                    const uint32_t boff = (base_off + (uint32_t)(dl * (int)wd)) * 8u;  // 0 <= dl < T
+                    // Rows are stored in pairs (dl even, dl + 1; dl has the
+                    // parity of i) where the registers allow: a row of wd
+                    // words ends inside a 32-byte sector unless 4 | wd, and
+                    // storing the two rows that share it together writes that
+                    // sector once; stored a sweep iteration apart, a busy L2
+                    // often wrote it back twice (17% more DRAM writes on the
+                    // 512-lattice ensemble).  With forcing or obstacles at
+                    // depth 5, and for FHP-III, the held row would spill.
+                    if constexpr (!kPairs) {
+                        const uint32_t boff = (base_off + (uint32_t)(dl * (int)wd)) * 8u;  // 0 <= dl < T
 #pragma unroll
-                    for (int c = 0; c < 7; c++) *(GlobalU64*)((GlobalChar*)(out + c * ps) + boff) = Y.p[c];
+                        for (int c = 0; c < 7; c++) *(GlobalU64*)((GlobalChar*)(out + c * ps) + boff) = Y.p[c];
+                    } else if constexpr (PAR == 0) {
+#pragma unroll
+                        for (int c = 0; c < 7; c++) held[c] = Y.p[c];
+                    } else {
+                        const uint32_t boff = (base_off + (uint32_t)(dl * (int)wd)) * 8u;  // 1 <= dl < T
+                        const uint32_t hoff = boff - wd * 8u;                             // row dl - 1
+#pragma unroll
+                        for (int c = 0; c < 7; c++) {
+                            *(GlobalU64*)((GlobalChar*)(out + c * ps) + hoff) = held[c];
+                            *(GlobalU64*)((GlobalChar*)(out + c * ps) + boff) = Y.p[c];
+                        }
+                    }
                 }
             });
         };
