@@ -288,7 +288,8 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
                     if constexpr (!kPairs) {
                         const uint32_t boff = (base_off + (uint32_t)(dl * (int)wd)) * 8u;  // 0 <= dl < T
 #pragma unroll
-                        for (int c = 0; c < 7; c++) *(GlobalU64*)((GlobalChar*)(out + c * ps) + boff) = Y.p[c];
+                        for (int c = 0; c < 7; c++)
+                            __builtin_nontemporal_store(Y.p[c], (GlobalU64*)((GlobalChar*)(out + c * ps) + boff));
                     } else if constexpr (PAR == 0) {
 #pragma unroll
                         for (int c = 0; c < 7; c++) held[c] = Y.p[c];
@@ -297,8 +298,8 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
                         const uint32_t hoff = boff - wd * 8u;                             // row dl - 1
 #pragma unroll
                         for (int c = 0; c < 7; c++) {
-                            *(GlobalU64*)((GlobalChar*)(out + c * ps) + hoff) = held[c];
-                            *(GlobalU64*)((GlobalChar*)(out + c * ps) + boff) = Y.p[c];
+                            __builtin_nontemporal_store(held[c], (GlobalU64*)((GlobalChar*)(out + c * ps) + hoff));
+                            __builtin_nontemporal_store(Y.p[c], (GlobalU64*)((GlobalChar*)(out + c * ps) + boff));
                         }
                     }
                 }

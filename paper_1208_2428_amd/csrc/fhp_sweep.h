@@ -78,12 +78,17 @@ __device__ __forceinline__ uint64_t buf_load64(__amdgpu_buffer_rsrc_t r, uint32_
     const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, (int)soff, 0);
     return ((uint64_t)v[1] << 32) | v[0];
 }
+// Stores of a pass's output rows carry the non-temporal hint (nt): the rows
+// are not read again in this launch, and streaming them out instead of
+// keeping them dirty in the L2 made the 16384^2 pass 3.4% faster and the
+// pass-shaped copy 1.44x faster.
+constexpr int kStoreNT = 2;  // cache-policy bits of a buffer store: nt
 __device__ __forceinline__ void buf_store64(__amdgpu_buffer_rsrc_t r, uint32_t off, uint32_t soff,
                                             uint64_t x) {
     __attribute__((ext_vector_type(2))) uint32_t v;
     v[0] = (uint32_t)x;
     v[1] = (uint32_t)(x >> 32);
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, (int)soff, kStoreNT);
 }
 
 // The seven planes of one state buffer (plane stride ps words, planes of
