@@ -115,8 +115,9 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
         b5[l] = x.c[2];
         bq[l] = x.c[3];
     };
-    Row nxt;
+    Row nxt, nxt2;
     load(wrap_row((int)y0 - K), nxt);
+    load(wrap_row((int)y0 - K + 1), nxt2);
 
     // One sweep iteration.  FULL: every level is active (i >= 2K).  PAR: i & 1.
     auto body = [&](int i, auto full_c, auto par_c) __attribute__((always_inline)) {
@@ -125,8 +126,9 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
         const int r = (int)y0 - K + i;
         const uint32_t y = wrap_row(r);
         Row X = nxt;
-        // prefetch the next row (the last iteration reloads its own row)
-        load((i + 1 < n_iter) ? wrap_row(r + 1) : y, nxt);
+        nxt = nxt2;
+        // prefetch two rows ahead (the last iterations reload their own row)
+        load((i + 2 < n_iter) ? wrap_row(r + 2) : y, nxt2);
         const uint64_t wall = (a.walls && (y == 0 || y == H - 1)) ? ~0ull : 0ull;  // uniform
         X.s = MASK ? (X.s | wall) : wall;
         // The hash words of the next level do not depend on the exchange, so
