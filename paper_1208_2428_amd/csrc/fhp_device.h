@@ -142,6 +142,44 @@ FHP_HD void collide_fhp12(const uint32_t a[7], const Counts& K, uint32_t s, uint
     o[6] = lop3<kA ^ (kB & ~kC)>(r, c3, s);                               // r ^ (c3 & ~s)
 }
 
+// FHP-II collision of 32 nodes with the rule masks formed from the class
+// counts alone (19 operations where counts() + collide_fhp12 take 21).  With
+// e, o the particle counts of the even and odd class (se/ce, so/co their
+// parity and carry bits) and x = se ^ so (the total is odd):
+//   R1, a head-on pair alone: e = o = 1 and an opposite pair present;
+//   R2, three in one class without rest: e, o in {0, 3} and x (e != o);
+//   R3: with rest, one particle (x and no carry); without rest, two
+//       particles in one class (no parity bit, exactly one carry).
+// The per-channel outputs are those of collide_fhp12.
+FHP_HD void collide_fhp2(const uint32_t a[7], uint32_t s, uint32_t chi, uint32_t o[7]) {
+    const uint32_t r = a[6];
+    const uint32_t se = xor3(a[0], a[2], a[4]), ce = maj3(a[0], a[2], a[4]);
+    const uint32_t so = xor3(a[1], a[3], a[5]), co = maj3(a[1], a[3], a[5]);
+    const uint32_t x = se ^ so;
+    const uint32_t one = lop3<kA & ~kB & ~kC>(x, ce, co);          // one particle
+    const uint32_t two_cls = lop3<~kA & ~kB & kC>(se, so, ce ^ co);  // two in one class
+    const uint32_t c3 = mux3(r, one, two_cls);                       // R3
+    uint32_t pp = a[0] & a[3];
+    pp = lop3<kA | (kB & kC)>(pp, a[1], a[4]);
+    pp = lop3<kA | (kB & kC)>(pp, a[2], a[5]);                      // an opposite pair
+    const uint32_t e1o1 = lop3<kA & kB & ~kC>(se, so, ce);          // with ~co: e = o = 1
+    const uint32_t r1 = lop3<kA & ~kB & kC>(e1o1, co, pp);          // R1
+    const uint32_t w = lop3<kA & ~(kB ^ kC)>(x, se, ce);            // x, e in {0, 3}
+    const uint32_t r2 = lop3<kA & ~(kB ^ kC)>(w, so, co);           // and o in {0, 3}
+    const uint32_t c12 = lop3<kA | (kB & ~kC)>(r1, r2, r);          // R1 or R2 (no rest)
+    const uint32_t zc = lop3<(kA & ~kB) | (~kA & kC)>(c12, chi, r); // c12 ? ~chi : r
+    const uint32_t any = c12 | c3;
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        const uint32_t am = a[(j + 5) % 6], ap = a[(j + 1) % 6];
+        const uint32_t z = lop3<kA ^ (kB & kC)>(zc, c12, am);
+        const uint32_t sp = lop3<(((kA ^ kB) & kC) | (~(kA ^ kB) & kA)) & 0xFF>(am, ap, z);
+        const uint32_t fl = mux3(any, sp, a[j]);
+        o[j] = mux3(s, a[(j + 3) % 6], fl);
+    }
+    o[6] = lop3<kA ^ (kB & ~kC)>(r, c3, s);
+}
+
 // Collision-saturated FHP-III.  Nodes of mass >= 4 are handled through their
 // complement (particle-hole duality: T(s) = ~T(~s)), so the rules below act
 // on mass <= 3 only: FHP-II, plus for every spectator position j the cycle
@@ -225,6 +263,8 @@ FHP_HD void update32(const uint32_t a[7], uint32_t s, uint32_t chi, uint32_t coi
                      uint32_t o[7]) {
     if constexpr (RULES == kRulesFHP3) {
         collide_fhp3(a, s, chi, o);
+    } else if constexpr (RULES == kRulesFHP2) {
+        collide_fhp2(a, s, chi, o);
     } else {
         collide_fhp12<RULES>(a, counts(a), s, chi, o);
     }
