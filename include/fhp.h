@@ -50,6 +50,13 @@
  * message for the calling thread's last failure.  A handle is not thread-safe.
  * Work is enqueued on the handle's HIP stream; asynchronous device faults are
  * reported as FHP_E_DEVICE by the next call that synchronises.
+ *
+ * Testing the error paths: the environment variable FHP_FAULT, read once per
+ * process, injects host-side failures that never reach the device --
+ * "launch@N": every fhp_step launch after the first N fails (FHP_E_DEVICE; the
+ * passes before it are kept and the time counter matches them); "alloc": the
+ * pinned staging buffer of fhp_batch_create and fhp_pool_create is not
+ * allocated (FHP_E_DEVICE, nothing is left allocated).
  */
 #ifndef FHP_H
 #define FHP_H

@@ -50,6 +50,36 @@ int upload_bytes(fhp_sim* s, const uint8_t* host, int mask_only) {
 }
 }  // namespace
 
+namespace {
+struct FaultPlan {
+    bool launch = false, alloc = false;
+    long long launch_after = 0;
+    long long launches = 0;
+};
+FaultPlan& fault_plan() {
+    static FaultPlan plan = [] {
+        FaultPlan f;
+        const char* v = getenv("FHP_FAULT");
+        if (!v) return f;
+        if (!strncmp(v, "launch", 6)) {
+            f.launch = true;
+            if (v[6] == '@') f.launch_after = atoll(v + 7);
+        } else if (!strcmp(v, "alloc")) {
+            f.alloc = true;
+        }
+        return f;
+    }();
+    return plan;
+}
+}  // namespace
+
+bool fault_launch() {
+    FaultPlan& f = fault_plan();
+    return f.launch && f.launches++ >= f.launch_after;
+}
+
+bool fault_alloc() { return fault_plan().alloc; }
+
 int fail(int code, const char* fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
@@ -267,6 +297,7 @@ int fhp_step(fhp_sim* s, uint64_t n) {
     const uint32_t T = s->band ? s->band : default_band(s->L.H, s->L.wd, s->simds);
     while (n > 0) {
         uint32_t k = (n >= depth) ? depth : (uint32_t)n;
+        if (fault_launch()) return hip_fail(hipErrorLaunchFailure, "step (injected by FHP_FAULT)");
         if (k == 1)
             FHP_HIP_TRY(launch_step1(s->buf[s->cur], s->buf[1 - s->cur], L, s->D, s->t, s->st),
                         "step");

@@ -552,6 +552,7 @@ int engine_init(Engine* e, uint64_t* tables, uint32_t members, uint32_t segs, hi
     e->st = st;
     e->stage_bytes = sizeof(BatchHeader) + (size_t)members * sizeof(MemberDesc) +
                      (size_t)segs * sizeof(GroupDesc) + max_waves(segs) * sizeof(WaveDesc);
+    if (fault_alloc()) return hip_fail(hipErrorOutOfMemory, "pinned (injected by FHP_FAULT)");
     FHP_HIP_TRY(hipHostMalloc((void**)&e->stage, e->stage_bytes, hipHostMallocDefault), "pinned");
     FHP_HIP_TRY(hipEventCreateWithFlags(&e->staged, hipEventDisableTiming), "event");
     FHP_HIP_TRY(launch_fill_u64((uint64_t*)e->done, (segs + 1) / 2, 0, st), "clear");
@@ -1045,6 +1046,7 @@ int fhp_pool_create(void* dev_arena, size_t arena_bytes, uint32_t max_slots, uin
     pl->aux = a;
     int rc = engine_init(&pl->eng, a + kAuxWords, max_slots, max_bands, (hipStream_t)hip_stream);
     if (rc) {
+        engine_free(&pl->eng);
         delete pl;
         return rc;
     }

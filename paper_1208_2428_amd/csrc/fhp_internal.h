@@ -52,6 +52,16 @@ int hip_fail(hipError_t e, const char* what);
         if (e_ != hipSuccess) return ::fhp::hip_fail(e_, what); \
     } while (0)
 
+// Host-side fault injection for tests of the error paths, from the
+// environment variable FHP_FAULT, read once per process:
+//   "launch@N": single-lattice step launches after the first N fail with
+//               hipErrorLaunchFailure without reaching the device;
+//   "alloc":    the pinned staging buffer of batches and pools is not
+//               allocated (hipErrorOutOfMemory).
+// Unset or empty: no faults.  The GPU never sees an injected fault.
+bool fault_launch();  // true when this launch is to fail (counts launches)
+bool fault_alloc();
+
 int validate(const fhp_params* p);
 Layout layout_for(uint32_t W, uint32_t H);
 uint32_t default_depth(uint32_t wd);

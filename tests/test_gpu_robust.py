@@ -8,6 +8,10 @@ the dynamics needs, and the hash keys on (t, y, word) only.
 
 Cancellation: a pool job released while it still has steps left frees its
 memory for the next job; the jobs that stay resident are unaffected.
+
+Faults injected on the host (FHP_FAULT) are reported as FHP_E_DEVICE and leave
+a consistent state; garbage in the workspace outside the lattice's own words
+changes no result.
 """
 import numpy as np
 import pytest
@@ -113,3 +117,100 @@ def test_released_job_frees_memory_and_survivors_are_unaffected():
     np.testing.assert_array_equal(got[3], st)
     assert pool.usage()["active"] == 0
     pool.close()
+
+
+# ---------------------------------------------------------------- injected faults
+# FHP_FAULT (read by the library once per process) makes the host side fail a
+# step launch or the pinned staging allocation without anything reaching the
+# device; each case runs in a child process of its own.
+
+_FAULT_LAUNCH = r"""
+import numpy as np, oracle
+from paper_1208_2428_amd import Sim
+from paper_1208_2428_amd._binding import FhpError, E_DEVICE
+W, H = 256, 64
+s = Sim(W, H, seed=7, fill=0.3, force_rate=1e-2, walls=True, depth=5)
+try:
+    s.step(12)          # the first pass (5 steps) runs, the second launch fails
+    raise SystemExit("no error")
+except FhpError as e:
+    assert e.code == E_DEVICE and "injected" in str(e), e
+assert s.t == 5, s.t
+ref = oracle.init(W, H, 7, 0.3, walls=True)
+ref, _ = oracle.run(ref, 0, 5, 7, 1e-2)
+assert np.array_equal(s.get_state(), ref)
+print("FAULT-LAUNCH-OK")
+"""
+
+_FAULT_ALLOC = r"""
+import numpy as np, oracle
+from paper_1208_2428_amd import Batch, Pool, Sim
+from paper_1208_2428_amd._binding import FhpError, E_DEVICE
+for make in (lambda: Batch([dict(width=128, height=16, seed=1, fill=0.2)]),
+             lambda: Pool(Pool.arena_bytes_for(4, 64, 1 << 24), max_slots=4, max_bands=64)):
+    try:
+        make()
+        raise SystemExit("no error")
+    except FhpError as e:
+        assert e.code == E_DEVICE and "injected" in str(e), e
+s = Sim(128, 16, seed=1, fill=0.2)   # single lattices need no staging: unaffected
+s.step(7)
+ref = oracle.init(128, 16, 1, 0.2)
+ref, _ = oracle.run(ref, 0, 7, 1, 0.0)
+assert np.array_equal(s.get_state(), ref)
+print("FAULT-ALLOC-OK")
+"""
+
+
+@pytest.mark.parametrize("fault,code,token", [("launch@1", _FAULT_LAUNCH, "FAULT-LAUNCH-OK"),
+                                              ("alloc", _FAULT_ALLOC, "FAULT-ALLOC-OK")],
+                         ids=["launch", "alloc"])
+def test_injected_fault_is_reported_and_leaves_a_consistent_state(fault, code, token):
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, FHP_FAULT=fault, PYTHONPATH=root)
+    say("injected fault", fault)
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       timeout=300, cwd=root)
+    assert r.returncode == 0 and token in r.stdout, r.stdout[-2000:] + r.stderr[-2000:]
+
+
+@pytest.mark.parametrize("W,H,K", [(192, 10, 5), (320, 34, 3), (64, 6, 2), (4096, 14, 5)])
+def test_garbage_outside_the_lattice_changes_nothing(W, H, K):
+    """Poison halo: random bits in every word of the workspace that holds no
+    node of the lattice -- the padding after each plane, the padding of the
+    obstacle plane and the whole idle buffer -- leave every pass equal to the
+    oracle's (the kernels read only the lattice's own words and wrap at its
+    edges)."""
+    import torch
+    say("poison", W, H, K)
+    rng = np.random.default_rng(W * H + K)
+    mask = (rng.random((H, W)) < 0.1).astype(np.uint8)
+    f = 1.0 / 90
+    s = Sim(W, H, seed=5, fill=0.35, force_rate=f, walls=True, solid=mask, depth=K)
+    st0 = s.get_state()
+    words = H * W // 64
+    plane = (words + 31) // 32 * 32
+    ws = s.workspace.view(torch.int64)
+    junk = torch.from_numpy(rng.integers(-2**63, 2**63 - 1, size=15 * plane, dtype=np.int64)).to(ws.device)
+    cur = 0  # a new lattice holds its state in buffer 0
+    for buf in (0, 1):
+        for c in range(7):
+            base = (buf * 7 + c) * plane
+            if buf == cur:
+                ws[base + words: base + plane] = junk[base + words: base + plane]
+            else:
+                ws[base: base + plane] = junk[base: base + plane]
+    ws[14 * plane + words: 15 * plane] = junk[14 * plane + words: 15 * plane]
+    torch.cuda.synchronize()
+    # (no get_state here: it stages through the idle buffer, overwriting the junk)
+    assert s.digest() == oracle.digest(st0)  # the lattice's own words untouched
+    ref, t = st0, 0
+    for n in (K, 2 * K + 1, 1, K):
+        s.step(n)
+        ref, _ = oracle.run(ref, t, n, 5, f, threads=THREADS)
+        t += n
+        np.testing.assert_array_equal(s.get_state(), ref, err_msg=f"t={t}")
+    s.close()
