@@ -129,19 +129,19 @@ Layout layout_for(uint32_t W, uint32_t H) {
 // depth 5 moves 18% fewer bytes per step than depth 4 for 3% more halo work,
 // measured 3-6% faster, and is near both that bandwidth and the VALU issue
 // limit.
-uint32_t default_depth(uint32_t wd) { return wd <= kMaxBlockedWords ? FHP_MAX_DEPTH : 1; }
 
 // Default band height of the blocked kernel, from occupancy: the largest even
 // height up to 32 rows whose bands give every SIMD two waves (a band's
 // workgroup holds ceil(wd / 64) waves); if that takes bands of 2 rows, the
-// largest that gives every SIMD one wave.  Shorter bands cost halo work
-// (1 + (K - 1) / T level-rows per row, K halo rows loaded on each side), fewer
-// waves leave SIMDs idle.  Measured at K = 5 (node-updates/s by band height):
-// 16384^2 (four waves per band) 32 rows 9.9e12, 24-64 rows 7.7e12-9.4e12;
-// 8192^2 (two) 4, 8, 16, 32 rows 5.10e12, 7.54e12, 5.37e12, 4.28e12; 4096^2
-// (one) 2, 4, 8, 32 rows 2.98e12, 3.61e12, 2.88e12, 1.20e12; 2048^2 (one, half
-// used) 2, 4 rows 1.14e12, 0.93e12.  The rule picks 32, 8, 4 and 2.
-uint32_t default_band(uint32_t H, uint32_t wd, uint32_t simds) {
+// largest that gives every SIMD one wave (*one_wave set).  Shorter bands cost
+// halo work (1 + (K - 1) / T level-rows per row, K halo rows loaded on each
+// side), fewer waves leave SIMDs idle.  Measured at K = 5 (node-updates/s by
+// band height): 16384^2 (four waves per band) 32 rows 9.9e12, 24-64 rows
+// 7.7e12-9.4e12; 8192^2 (two) 4, 8, 16, 32 rows 5.10e12, 7.54e12, 5.37e12,
+// 4.28e12; 4096^2 (one) 2, 4, 8, 32 rows 2.98e12, 3.61e12, 2.88e12, 1.20e12;
+// 2048^2 (one, half used) 2, 4 rows 1.14e12, 0.93e12.  The rule picks 32, 8, 4
+// and 2.
+static uint32_t band_rule(uint32_t H, uint32_t wd, uint32_t simds, bool* one_wave) {
     const uint64_t waves = (wd + 63) / 64;
     auto largest = [&](uint64_t need) -> uint32_t {  // 0 when no height gives `need` waves
         for (uint32_t T = 32; T >= 2; T -= 2)
@@ -149,11 +149,31 @@ uint32_t default_band(uint32_t H, uint32_t wd, uint32_t simds) {
         return 0;
     };
     uint32_t T = largest(2ull * simds);
-    if (T < 4) {
+    *one_wave = T < 4;
+    if (*one_wave) {
         const uint32_t T1 = largest(simds);
         T = T1 > 2 ? T1 : 2;
     }
     return H < T ? H : T;
+}
+
+uint32_t default_band(uint32_t H, uint32_t wd, uint32_t simds) {
+    bool one_wave;
+    return band_rule(H, wd, simds, &one_wave);
+}
+
+// Default depth: FHP_MAX_DEPTH, except on lattices too small to give every
+// SIMD two waves, where a pass is bound by the latency of its level chain
+// rather than by memory and 3 steps per pass (25% less halo work than 5 at
+// 4-row bands) are faster: 4096^2 channel flow at K = 2..5 measured 4.87e12,
+// 4.95e12, 4.72e12 and 4.56e12 node-updates/s, 2048^2 at 2-row bands 1.45e12,
+// 1.49e12, 1.40e12 and 1.29e12.  Rows wider than the blocked kernel takes run
+// single steps.
+uint32_t default_depth(uint32_t H, uint32_t wd, uint32_t simds) {
+    if (wd > kMaxBlockedWords) return 1;
+    bool one_wave;
+    band_rule(H, wd, simds, &one_wave);
+    return one_wave ? 3 : FHP_MAX_DEPTH;
 }
 
 Dyn dyn_for(const fhp_params* p) {
@@ -200,9 +220,9 @@ int sim_setup(fhp_sim* s, const fhp_params* p, uint64_t* planes, const Layout& l
     s->L.ps = lay.plane_words;
     s->L.walls = p->walls == FHP_WALLS_CHANNEL;
     s->D = dyn_for(p);
-    s->depth = default_depth(s->L.wd);
-    s->band = 0;
     s->simds = device_simds();
+    s->depth = default_depth(s->L.H, s->L.wd, s->simds);
+    s->band = 0;
 
     FHP_HIP_TRY(launch_fill_u64(s->S, lay.plane_words, 0, st), "clear solid plane");
     s->has_mask = 0;
@@ -262,7 +282,7 @@ int fhp_set_depth(fhp_sim* s, uint32_t k) {
     if (k > FHP_MAX_DEPTH) return fail(FHP_E_INVAL, "depth %u above %u", k, FHP_MAX_DEPTH);
     if (k > 1 && s->L.wd > kMaxBlockedWords)
         return fail(FHP_E_INVAL, "depth %u needs width <= %u", k, 64 * kMaxBlockedWords);
-    s->depth = k ? k : default_depth(s->L.wd);
+    s->depth = k ? k : default_depth(s->L.H, s->L.wd, s->simds);
     return FHP_OK;
 }
 

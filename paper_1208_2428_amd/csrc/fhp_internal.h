@@ -64,7 +64,7 @@ bool fault_alloc();
 
 int validate(const fhp_params* p);
 Layout layout_for(uint32_t W, uint32_t H);
-uint32_t default_depth(uint32_t wd);
+uint32_t default_depth(uint32_t H, uint32_t wd, uint32_t simds);
 uint32_t default_band(uint32_t H, uint32_t wd, uint32_t simds);
 // Hash keys, forcing threshold and modes of the dynamics of *p.
 Dyn dyn_for(const fhp_params* p);

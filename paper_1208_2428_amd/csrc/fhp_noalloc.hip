@@ -93,9 +93,10 @@ extern "C" int fhp_step_noalloc(const fhp_params* p, const uint64_t* dev_in, uin
     L.walls = p->walls == FHP_WALLS_CHANNEL;
     L.S = dev_solid;
     const Dyn D = dyn_for(p);
-    uint32_t K = depth ? depth : default_depth(wd);
+    const uint32_t simds = device_simds();
+    uint32_t K = depth ? depth : default_depth(L.H, wd, simds);
     if (D.rules == FHP_RULES_FHP3 && K > kMaxDepthFHP3) K = kMaxDepthFHP3;
-    const uint32_t T = default_band(L.H, wd, device_simds());
+    const uint32_t T = default_band(L.H, wd, simds);
     // Passes of K steps (the last one shorter), alternating between dev_out
     // and the scratch buffer so that the last pass writes dev_out.
     uint64_t passes = (n + K - 1) / K;

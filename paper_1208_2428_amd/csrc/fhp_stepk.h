@@ -48,9 +48,20 @@ struct StepkArgs {
     uint64_t t0;           // steps done before this pass
     uint64_t key_chir, key_force, thr_force;
     uint32_t chi_and, chi_or;  // chirality word = (hash & chi_and) | chi_or, per 32-bit half
+    uint32_t xcd_runs;         // give each XCD a contiguous run of bands (see band_of)
 };
 
 namespace {
+
+// Band processed by workgroup b of nb.  Workgroups are dispatched round-robin
+// over the 8 XCDs (b to XCD b mod 8).  With `runs` set, XCD x instead takes a
+// contiguous run of bands, so that the halo rows a band shares with its
+// neighbours are read through one L2.
+__device__ inline uint32_t band_of(uint32_t b, uint32_t nb, uint32_t runs) {
+    if (!runs) return b;
+    const uint32_t q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
 
 constexpr size_t kStepkLdsBytes = 2 * 4 * kMaxBlockedWords * sizeof(uint32_t);
 
@@ -67,11 +78,7 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
     const uint32_t wl = w ? w - 1 : a.wd - 1;
     const uint32_t wr = (w + 1 == a.wd) ? 0 : w + 1;
     const uint32_t H = a.H;
-    // Bands in launch order: workgroups go round-robin over the 8 XCDs, so
-    // neighbouring bands run on different XCDs at the same time.  Giving each
-    // XCD a contiguous run of bands instead measured 8% slower at K = 4 and
-    // 19% slower at K = 2 on the 16384^2 lattice.
-    const uint32_t y0 = blockIdx.x * a.T;
+    const uint32_t y0 = band_of(blockIdx.x, gridDim.x, a.xcd_runs) * a.T;
     const uint32_t rows = min(a.T, H - y0);
     const int n_iter = (int)rows + 2 * K;
     const uint64_t base_chi = word_base(a.key_chir, w);

@@ -19,6 +19,13 @@ hipError_t launch_stepk(uint32_t K, const uint64_t* in, uint64_t* out, const Lat
     a.thr_force = D.thr_force;
     a.chi_and = (D.chir_mode == FHP_CHIR_HASH) ? ~0u : 0u;
     a.chi_or = (D.chir_mode == FHP_CHIR_ONE) ? ~0u : 0u;
+    // Contiguous runs of bands per XCD (band_of) where bands are one wave or
+    // less and short, so that each row is read by several neighbouring bands:
+    // on 4096^2 at K = 5 +19%, +8%, +6%, +4% and +1% for 2-, 4-, 6-, 8- and
+    // 16-row bands, on 2048^2 +5% to +9%.  Taller bands lose by it (32-row
+    // bands of a 4096 x 65536 lattice -25%, 16384^2 at 16 and 32 rows -10% and
+    // -8%), and rows of 128 words gain nothing at 4 or 8 rows.
+    a.xcd_runs = (L.wd <= 64 && a.T <= 8) ? 1u : 0u;
     if (planes_wide(L.ps)) return launch_stepk_wide(K, in, out, L, a, D.rules, st);
     if (L.wd == 64) return launch_stepk_wave(K, in, out, L, a, D.rules, st);
     return launch_depth<false>(K, in, out, L, a, D.rules, st);

@@ -134,3 +134,57 @@ def test_one_wave_rows(band, K, rules):
         np.testing.assert_array_equal(s.get_state(), ref, err_msg=f"t={t}")
     assert s.digest() == oracle.digest(ref)
     s.close()
+
+
+@pytest.mark.parametrize("W,H,band", [(2048, 1002, 6), (4096, 262, 4), (1024, 4098, 8), (512, 130, 2)])
+@pytest.mark.parametrize("K", [3, 5])
+def test_band_runs_per_xcd(W, H, band, K):
+    """Short bands (at most 8 rows) on rows of at most 64 words go to the
+    XCDs in contiguous runs instead of launch order.  Band counts that are not
+    a multiple of 8 (167, 66, 513, 65 here) and a short last band must still
+    cover every row exactly once: every pass equals the oracle."""
+    say("xcd runs", W, H, band, K)
+    rng = np.random.default_rng(W + H + band + K)
+    st = make_state(rng, W, H, "walls+force")
+    f = 1.0 / 90
+    s = Sim(W, H, seed=13, force_rate=f, walls=True, depth=K, band=band)
+    assert s.band == band
+    s.set_state(st, t=1)
+    ref, t = st.copy(), 1
+    for n in (K, 2 * K + 1):
+        s.step(n)
+        ref, _ = oracle.run(ref, t, n, 13, f, threads=THREADS)
+        t += n
+        np.testing.assert_array_equal(s.get_state(), ref, err_msg=f"t={t}")
+    s.close()
+
+
+def test_default_depth_and_band():
+    """The default depth is 5 steps per pass, or 3 on lattices too small to
+    give every SIMD two waves; the default band is the largest even height up
+    to 32 rows that gives every SIMD two waves (else one)."""
+    import torch
+    simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+
+    def expected(W, H):
+        waves = -(-W // 4096)
+
+        def largest(need):
+            for T in range(32, 1, -2):
+                if -(-H // T) * waves >= need:
+                    return T
+            return 0
+        T = largest(2 * simds)
+        one = T < 4
+        if one:
+            T = max(largest(simds), 2)
+        return (3 if one else 5), min(T, H)
+
+    for W, H in [(4096, 4096), (2048, 2048), (8192, 8192), (16384, 16384), (4096, 65536), (256, 256)]:
+        s = Sim(W, H, seed=1)
+        assert (s.depth, s.band) == expected(W, H), (W, H)
+        s.depth = 2
+        assert s.depth == 2
+        s.depth = 0  # back to the default
+        assert s.depth == expected(W, H)[0]
+        s.close()
