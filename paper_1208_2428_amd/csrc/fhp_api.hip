@@ -323,7 +323,8 @@ int fhp_step(fhp_sim* s, uint64_t n) {
                         "step");
         else
             FHP_HIP_TRY(
-                launch_stepk(k, s->buf[s->cur], s->buf[1 - s->cur], L, s->D, s->t, T, s->st),
+                launch_stepk(k, s->buf[s->cur], s->buf[1 - s->cur], L, s->D, s->t, T, s->simds,
+                             s->st),
                 "step");
         s->cur ^= 1;
         s->t += k;

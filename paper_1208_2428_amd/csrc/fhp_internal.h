@@ -91,10 +91,10 @@ hipError_t launch_observe_blocks(const uint64_t* planes, const Lattice& L, uint3
 hipError_t launch_digest(const uint64_t* planes, const Lattice& L, uint64_t* acc, hipStream_t st);
 hipError_t launch_step1(const uint64_t* in, uint64_t* out, const Lattice& L, const Dyn& D,
                         uint64_t t, hipStream_t st);
-// K steps in one pass (fhp_stepk.hip); bands of T rows, one workgroup per band.
-// Needs L.wd <= kMaxBlockedWords.
+// K steps in one pass (fhp_stepk.hip); bands of T rows, one workgroup per band,
+// on a device of `simds` SIMDs.  Needs L.wd <= kMaxBlockedWords.
 hipError_t launch_stepk(uint32_t K, const uint64_t* in, uint64_t* out, const Lattice& L,
-                        const Dyn& D, uint64_t t, uint32_t T, hipStream_t st);
+                        const Dyn& D, uint64_t t, uint32_t T, uint32_t simds, hipStream_t st);
 
 }  // namespace fhp
 

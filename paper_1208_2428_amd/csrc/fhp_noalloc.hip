@@ -107,7 +107,7 @@ extern "C" int fhp_step_noalloc(const fhp_params* p, const uint64_t* dev_in, uin
         if (k == 1)
             FHP_HIP_TRY(launch_step1(src, dst, L, D, t, st), "step");
         else
-            FHP_HIP_TRY(launch_stepk(k, src, dst, L, D, t, T, st), "step");
+            FHP_HIP_TRY(launch_stepk(k, src, dst, L, D, t, T, simds, st), "step");
         src = dst;
         t += k;
         n -= k;

@@ -66,8 +66,11 @@ __device__ inline uint32_t band_of(uint32_t b, uint32_t nb, uint32_t runs) {
 constexpr size_t kStepkLdsBytes = 2 * 4 * kMaxBlockedWords * sizeof(uint32_t);
 
 // ONE_WAVE: rows of exactly 64 words, one wave per band; the carries move
-// between lanes by DPP (gather_wave) instead of through LDS.
-template <int K, bool FORCE, bool MASK, int RULES, bool WIDE, bool ONE_WAVE = false>
+// between lanes by DPP (gather_wave) instead of through LDS.  PRELOAD: the
+// 2K + 2 rows of the pipeline fill are loaded at once, for launches of at most
+// one wave per SIMD (see launch_stepk).
+template <int K, bool FORCE, bool MASK, int RULES, bool WIDE, bool ONE_WAVE = false,
+          bool PRELOAD = false>
 __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
                                                 uint64_t* __restrict__ out,
                                                 const uint64_t* __restrict__ S, StepkArgs a) {
@@ -122,20 +125,32 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
         b5[l] = x.c[2];
         bq[l] = x.c[3];
     };
-    Row nxt, nxt2;
-    load(wrap_row((int)y0 - K), nxt);
-    load(wrap_row((int)y0 - K + 1), nxt2);
+    // Rows are loaded two ahead of the sweep (nxt, nxt2).  With PRELOAD the
+    // rows of the whole pipeline fill are loaded before it instead: the fill
+    // iterations run few levels, so a wave that has its SIMD to itself would
+    // otherwise wait out most of each load's latency there.
+    constexpr int kPre = PRELOAD ? 2 * K + 2 : 2;
+    Row pre[kPre];
+    static_for<0, kPre - 1>([&](auto jc) __attribute__((always_inline)) {
+        constexpr int j = decltype(jc)::value;
+        load(wrap_row((int)y0 - K + j), pre[j]);
+    });
+    Row nxt = pre[kPre - 2], nxt2 = pre[kPre - 1];
 
     // One sweep iteration.  FULL: every level is active (i >= 2K).  PAR: i & 1.
-    auto body = [&](int i, auto full_c, auto par_c) __attribute__((always_inline)) {
+    // X: the row of level 0 in the preloaded fill; otherwise it is taken from
+    // the prefetch queue.
+    auto body = [&](int i, auto full_c, auto par_c, Row X) __attribute__((always_inline)) {
         constexpr bool FULL = decltype(full_c)::value;
         constexpr int PAR = decltype(par_c)::value;
         const int r = (int)y0 - K + i;
         const uint32_t y = wrap_row(r);
-        Row X = nxt;
-        nxt = nxt2;
-        // prefetch two rows ahead (the last iterations reload their own row)
-        load((i + 2 < n_iter) ? wrap_row(r + 2) : y, nxt2);
+        if constexpr (FULL || !PRELOAD) {
+            X = nxt;
+            nxt = nxt2;
+            // prefetch two rows ahead (the last iterations reload their own row)
+            load((i + 2 < n_iter) ? wrap_row(r + 2) : y, nxt2);
+        }
         const uint64_t wall = (a.walls && (y == 0 || y == H - 1)) ? ~0ull : 0ull;  // uniform
         X.s = MASK ? (X.s | wall) : wall;
         // The hash words of the next level do not depend on the exchange, so
@@ -202,76 +217,79 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
     using T = std::true_type;
     using P0 = std::integral_constant<int, 0>;
     using P1 = std::integral_constant<int, 1>;
-    int i = 0;
-    for (; i < 2 * K; i += 2) {  // pipeline fill (n_iter >= 2K + 2)
-        body(i, F{}, P0{});
-        body(i + 1, F{}, P1{});
-    }
+    // pipeline fill (n_iter >= 2K + 2)
+    static_for<0, K - 1>([&](auto jc) __attribute__((always_inline)) {
+        constexpr int j = 2 * decltype(jc)::value;
+        body(j, F{}, P0{}, pre[PRELOAD ? j : 0]);
+        body(j + 1, F{}, P1{}, pre[PRELOAD ? j + 1 : 0]);
+    });
+    int i = 2 * K;
     // Steady state, six rows per trip: a row's planes 3 and 4 stay live for
     // three iterations, and with two iterations per trip the compiler
     // rotates them through registers with moves (about 6 per word and level).
     for (; i + 6 <= n_iter; i += 6) {
-        body(i, T{}, P0{});
-        body(i + 1, T{}, P1{});
-        body(i + 2, T{}, P0{});
-        body(i + 3, T{}, P1{});
-        body(i + 4, T{}, P0{});
-        body(i + 5, T{}, P1{});
+        body(i, T{}, P0{}, nxt);
+        body(i + 1, T{}, P1{}, nxt);
+        body(i + 2, T{}, P0{}, nxt);
+        body(i + 3, T{}, P1{}, nxt);
+        body(i + 4, T{}, P0{}, nxt);
+        body(i + 5, T{}, P1{}, nxt);
     }
     for (; i < n_iter; i += 2) {  // rows is even, so n_iter - 2K is even
-        body(i, T{}, P0{});
-        body(i + 1, T{}, P1{});
+        body(i, T{}, P0{}, nxt);
+        body(i + 1, T{}, P1{}, nxt);
     }
 }
 
-template <bool WIDE, int K, bool FORCE, bool MASK, int RULES = kRulesFHP2, bool ONE_WAVE = false>
+template <bool WIDE, int K, bool FORCE, bool MASK, int RULES = kRulesFHP2, bool ONE_WAVE = false,
+          bool PRELOAD = false>
 hipError_t launch_k(const uint64_t* in, uint64_t* out, const Lattice& L, const StepkArgs& a,
                     hipStream_t st) {
     const uint32_t nt = (L.wd + 63) / 64 * 64;
     const uint32_t bands = (L.H + a.T - 1) / a.T;
     if constexpr (ONE_WAVE) {
         if (L.wd != 64) return hipErrorInvalidValue;
-        hipLaunchKernelGGL((k_stepk<K, FORCE, MASK, RULES, WIDE, true>), dim3(bands), dim3(64), 0,
-                           st, in, out, L.S, a);
+        hipLaunchKernelGGL((k_stepk<K, FORCE, MASK, RULES, WIDE, true, PRELOAD>), dim3(bands),
+                           dim3(64), 0, st, in, out, L.S, a);
     } else {
-        hipLaunchKernelGGL((k_stepk<K, FORCE, MASK, RULES, WIDE>), dim3(bands), dim3(nt),
-                           kStepkLdsBytes, st, in, out, L.S, a);
+        hipLaunchKernelGGL((k_stepk<K, FORCE, MASK, RULES, WIDE, false, PRELOAD>), dim3(bands),
+                           dim3(nt), kStepkLdsBytes, st, in, out, L.S, a);
     }
     return hipGetLastError();
 }
 
 // FHP-II has a kernel for every combination of forcing and obstacles; the
 // other rule sets use the forcing variant (a zero rate draws no coin).
-template <bool WIDE, int K, bool OW = false>
+template <bool WIDE, int K, bool OW = false, bool PL = false>
 hipError_t launch_k2(const uint64_t* in, uint64_t* out, const Lattice& L, const StepkArgs& a,
                      uint32_t rules, hipStream_t st) {
     const bool force = a.thr_force != 0, mask = L.S != nullptr;
     if (rules == kRulesFHP1)
-        return mask ? launch_k<WIDE, K, true, true, kRulesFHP1, OW>(in, out, L, a, st)
-                    : launch_k<WIDE, K, true, false, kRulesFHP1, OW>(in, out, L, a, st);
+        return mask ? launch_k<WIDE, K, true, true, kRulesFHP1, OW, PL>(in, out, L, a, st)
+                    : launch_k<WIDE, K, true, false, kRulesFHP1, OW, PL>(in, out, L, a, st);
     if (rules == kRulesFHP3) {
         if constexpr (K <= kMaxDepthFHP3)
-            return mask ? launch_k<WIDE, K, true, true, kRulesFHP3, OW>(in, out, L, a, st)
-                        : launch_k<WIDE, K, true, false, kRulesFHP3, OW>(in, out, L, a, st);
+            return mask ? launch_k<WIDE, K, true, true, kRulesFHP3, OW, PL>(in, out, L, a, st)
+                        : launch_k<WIDE, K, true, false, kRulesFHP3, OW, PL>(in, out, L, a, st);
         return hipErrorInvalidValue;
     }
-    if (force) return mask ? launch_k<WIDE, K, true, true, kRulesFHP2, OW>(in, out, L, a, st)
-                           : launch_k<WIDE, K, true, false, kRulesFHP2, OW>(in, out, L, a, st);
-    return mask ? launch_k<WIDE, K, false, true, kRulesFHP2, OW>(in, out, L, a, st)
-                : launch_k<WIDE, K, false, false, kRulesFHP2, OW>(in, out, L, a, st);
+    if (force) return mask ? launch_k<WIDE, K, true, true, kRulesFHP2, OW, PL>(in, out, L, a, st)
+                           : launch_k<WIDE, K, true, false, kRulesFHP2, OW, PL>(in, out, L, a, st);
+    return mask ? launch_k<WIDE, K, false, true, kRulesFHP2, OW, PL>(in, out, L, a, st)
+                : launch_k<WIDE, K, false, false, kRulesFHP2, OW, PL>(in, out, L, a, st);
 }
 
 // Launches the pass of depth K for buffers of the given width class
-// (OW: the one-wave kernel for rows of 64 words).
-template <bool WIDE, bool OW = false>
+// (OW: the one-wave kernel for rows of 64 words; PL: the preloaded fill).
+template <bool WIDE, bool OW = false, bool PL = false>
 hipError_t launch_depth(uint32_t K, const uint64_t* in, uint64_t* out, const Lattice& L, const StepkArgs& a,
                         uint32_t rules, hipStream_t st) {
     switch (K) {
-        case 1: return launch_k2<WIDE, 1, OW>(in, out, L, a, rules, st);
-        case 2: return launch_k2<WIDE, 2, OW>(in, out, L, a, rules, st);
-        case 3: return launch_k2<WIDE, 3, OW>(in, out, L, a, rules, st);
-        case 4: return launch_k2<WIDE, 4, OW>(in, out, L, a, rules, st);
-        case 5: return launch_k2<WIDE, 5, OW>(in, out, L, a, rules, st);
+        case 1: return launch_k2<WIDE, 1, OW, PL>(in, out, L, a, rules, st);
+        case 2: return launch_k2<WIDE, 2, OW, PL>(in, out, L, a, rules, st);
+        case 3: return launch_k2<WIDE, 3, OW, PL>(in, out, L, a, rules, st);
+        case 4: return launch_k2<WIDE, 4, OW, PL>(in, out, L, a, rules, st);
+        case 5: return launch_k2<WIDE, 5, OW, PL>(in, out, L, a, rules, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -285,5 +303,10 @@ hipError_t launch_stepk_wide(uint32_t K, const uint64_t* in, uint64_t* out, cons
 // The pass for rows of exactly 64 words, one wave per band (fhp_stepk_wave.hip).
 hipError_t launch_stepk_wave(uint32_t K, const uint64_t* in, uint64_t* out, const Lattice& L,
                              const StepkArgs& a, uint32_t rules, hipStream_t st);
+// The passes with the preloaded pipeline fill, for launches of at most one
+// wave per SIMD (fhp_stepk_preload.hip); one_wave as for launch_stepk_wave.
+hipError_t launch_stepk_preload(uint32_t K, const uint64_t* in, uint64_t* out, const Lattice& L,
+                                const StepkArgs& a, uint32_t rules, bool one_wave,
+                                hipStream_t st);
 
 }  // namespace fhp

@@ -6,7 +6,7 @@
 namespace fhp {
 
 hipError_t launch_stepk(uint32_t K, const uint64_t* in, uint64_t* out, const Lattice& L,
-                        const Dyn& D, uint64_t t, uint32_t T, hipStream_t st) {
+                        const Dyn& D, uint64_t t, uint32_t T, uint32_t simds, hipStream_t st) {
     StepkArgs a;
     a.H = L.H;
     a.wd = L.wd;
@@ -27,6 +27,12 @@ hipError_t launch_stepk(uint32_t K, const uint64_t* in, uint64_t* out, const Lat
     // -8%), and rows of 128 words gain nothing at 4 or 8 rows.
     a.xcd_runs = (L.wd <= 64 && a.T <= 8) ? 1u : 0u;
     if (planes_wide(L.ps)) return launch_stepk_wide(K, in, out, L, a, D.rules, st);
+    // At most one wave per SIMD: nothing hides a wave's load latency, and the
+    // preloaded pipeline fill pays: on 4096^2 +8% at K = 3 and +11% at K = 5
+    // (4-row bands), on 2048^2 +5%.  With two waves per SIMD the other wave
+    // hides it and the preload costs 1-5% (16384^2, 8192^2, 4096 x 65536).
+    const uint64_t waves = (uint64_t)((L.H + a.T - 1) / a.T) * ((L.wd + 63) / 64);
+    if (waves <= simds) return launch_stepk_preload(K, in, out, L, a, D.rules, L.wd == 64, st);
     if (L.wd == 64) return launch_stepk_wave(K, in, out, L, a, D.rules, st);
     return launch_depth<false>(K, in, out, L, a, D.rules, st);
 }

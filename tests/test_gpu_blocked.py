@@ -188,3 +188,31 @@ def test_default_depth_and_band():
         s.depth = 0  # back to the default
         assert s.depth == expected(W, H)[0]
         s.close()
+
+
+@pytest.mark.parametrize("W,band", [(64, 2), (1024, 4), (4096, 2), (4096, 6), (8192, 2)])
+@pytest.mark.parametrize("K", [2, 5])
+def test_preloaded_and_streamed_fill(W, band, K):
+    """A launch of at most one wave per SIMD loads the rows of its pipeline
+    fill at once; with more waves it streams them two rows ahead.  Lattices
+    with exactly as many band waves as the device has SIMDs, and with one band
+    more, take the two paths; both must equal the oracle after every pass."""
+    import torch
+    simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    waves_per_band = -(-W // 4096)
+    bands = simds // waves_per_band
+    for nb in (bands, bands + 1):
+        H = nb * band
+        say("fill", W, H, band, K, "bands", nb)
+        rng = np.random.default_rng(W + H + K)
+        st = make_state(rng, W, H, "walls+force")
+        f = 1.0 / 75
+        s = Sim(W, H, seed=5, force_rate=f, walls=True, depth=K, band=band)
+        s.set_state(st, t=2)
+        ref, t = st.copy(), 2
+        for n in (K, K + 1):
+            s.step(n)
+            ref, _ = oracle.run(ref, t, n, 5, f, threads=THREADS)
+            t += n
+            np.testing.assert_array_equal(s.get_state(), ref, err_msg=f"H={H} t={t}")
+        s.close()
