@@ -137,19 +137,45 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
     });
     Row nxt = pre[kPre - 2], nxt2 = pre[kPre - 1];
 
+    // Row bookkeeping, in scalar registers and kept incrementally (a wave that
+    // has its SIMD to itself issues every scalar instruction in place of a
+    // vector one).  Before iteration i, whose row is r = y0 - K + i,
+    // yq[j] = (r + 1 - j) mod H and hq[j] = row_term(0, yq[j]); an iteration
+    // shifts both windows by one and appends row r + 2.  Level l then computes
+    // row yq[2 + l], whose hash counter term is tq[l] + hq[2 + l].
+    constexpr int kWin = K + 3;
+    uint32_t yq[kWin];
+    uint64_t hq[kWin], tq[K + 1];
+    static_for<0, kWin - 1>([&](auto jc) __attribute__((always_inline)) {
+        constexpr int j = decltype(jc)::value;
+        yq[j] = wrap_row((int)y0 - K + 1 - j);
+        hq[j] = row_term(0, yq[j]);
+    });
+    static_for<1, K>([&](auto lc) __attribute__((always_inline)) {
+        constexpr int l = decltype(lc)::value;
+        tq[l] = row_term(a.t0 + (uint64_t)(l - 1), 0);
+    });
+    const uint64_t row_step = row_term(0, 1);
+
     // One sweep iteration.  FULL: every level is active (i >= 2K).  PAR: i & 1.
     // X: the row of level 0 in the preloaded fill; otherwise it is taken from
     // the prefetch queue.
     auto body = [&](int i, auto full_c, auto par_c, Row X) __attribute__((always_inline)) {
         constexpr bool FULL = decltype(full_c)::value;
         constexpr int PAR = decltype(par_c)::value;
-        const int r = (int)y0 - K + i;
-        const uint32_t y = wrap_row(r);
+        static_for<1, kWin - 1>([&](auto jc) __attribute__((always_inline)) {
+            constexpr int j = kWin - decltype(jc)::value;
+            yq[j] = yq[j - 1];
+            hq[j] = hq[j - 1];
+        });
+        yq[0] = (yq[1] + 1 == H) ? 0u : yq[1] + 1;
+        hq[0] = yq[0] ? hq[1] + row_step : 0ull;
+        const uint32_t y = yq[2];
         if constexpr (FULL || !PRELOAD) {
             X = nxt;
             nxt = nxt2;
             // prefetch two rows ahead (the last iterations reload their own row)
-            load((i + 2 < n_iter) ? wrap_row(r + 2) : y, nxt2);
+            load((i + 2 < n_iter) ? yq[0] : y, nxt2);
         }
         const uint64_t wall = (a.walls && (y == 0 || y == H - 1)) ? ~0ull : 0ull;  // uniform
         X.s = MASK ? (X.s | wall) : wall;
@@ -157,8 +183,9 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
         // they are formed between publishing a row and the barrier.
         uint64_t chi = 0, coin = 0;
         uint32_t up = 0;
-        auto hashes = [&](int l) __attribute__((always_inline)) {
-            const uint64_t R = in_sgprs(row_term(a.t0 + (uint64_t)(l - 1), wrap_row(r - l)));
+        auto hashes = [&](auto hc) __attribute__((always_inline)) {
+            constexpr int l = decltype(hc)::value;
+            const uint64_t R = in_sgprs(tq[l] + hq[2 + l]);
             chi = chir_word(mix64(base_chi + R), chi_and, a.chi_or);
             if (FORCE) {
                 const uint64_t hf = mix64(base_frc + R);
@@ -168,11 +195,11 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
         };
         constexpr bool odd0 = ((PAR + K) & 1) != 0;  // y0 even: parity of y
         if constexpr (ONE_WAVE) {
-            if (FULL || i >= 2) hashes(1);
+            if (FULL || i >= 2) hashes(std::integral_constant<int, 1>{});
             gather_wave<odd0>(X);
         } else {
             publish<odd0>(xch, slot, kMaxBlockedWords, lane, X);
-            if (FULL || i >= 2) hashes(1);
+            if (FULL || i >= 2) hashes(std::integral_constant<int, 1>{});
             gather<odd0>(xch, slot, kMaxBlockedWords, wl, wr, X);
         }
         bool have = true;  // X holds a new row of level l-1
@@ -186,7 +213,7 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
                     return;
                 }
             }
-            const uint32_t rho = wrap_row(r - l);
+            const uint32_t rho = yq[2 + l];
             constexpr bool odd = ((PAR + K + l) & 1) != 0;  // parity of rho
             uint64_t n[7];
             stream_in<odd>(a3[l], a4[l], ac[l], bp[l], b2[l], b5[l], X, n);
@@ -195,13 +222,13 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
             update<RULES>(n, sw, chi, coin, up, Y.p);
             Y.s = sw;
             push(lc, X);
-            if (l < K) {
+            if constexpr (l < K) {
                 if constexpr (ONE_WAVE) {
-                    if (FULL || i >= 2 * (l + 1)) hashes(l + 1);
+                    if (FULL || i >= 2 * (l + 1)) hashes(std::integral_constant<int, l + 1>{});
                     gather_wave<odd>(Y);
                 } else {
                     publish<odd>(xch, slot, kMaxBlockedWords, lane, Y);
-                    if (FULL || i >= 2 * (l + 1)) hashes(l + 1);
+                    if (FULL || i >= 2 * (l + 1)) hashes(std::integral_constant<int, l + 1>{});
                     gather<odd>(xch, slot, kMaxBlockedWords, wl, wr, Y);
                 }
                 X = Y;
