@@ -24,7 +24,9 @@ DEFAULT_BATCH_CANDIDATES = [
     dict(depth=k, band=b, group_threads=nt, passes_per_launch=ppl)
     for k in (1, 2, 3, 4, 5) for b in (8, 16, 32, 64) for nt in (64, 256) for ppl in (1, 0)
 ]
-DEFAULT_SIM_CANDIDATES = [dict(depth=k, band=b) for k in (1, 2, 3, 4, 5) for b in (4, 8, 16, 32, 64)]
+# 2- and 6-row bands: the best heights on lattices of 32- and 64-word rows
+# too small to give every SIMD two waves (2048^2, 4096^2)
+DEFAULT_SIM_CANDIDATES = [dict(depth=k, band=b) for k in (1, 2, 3, 4, 5) for b in (2, 4, 6, 8, 16, 32, 64)]
 
 
 def cache_path() -> str:
