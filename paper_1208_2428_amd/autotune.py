@@ -112,15 +112,16 @@ def tune_batch(batch, params: list[dict], candidates=None, steps: int = 24,
                use_cache: bool = True) -> dict:
     """Returns {"tiling": best candidate, "trials": [(candidate, s/step)]} and
     leaves `batch` set to the best tiling."""
+    cands = candidates or DEFAULT_BATCH_CANDIDATES
     key = (f"batch:{_gpu_name()}:{batch_signature(params)}:"
-           f"{_candidates_hash(DEFAULT_BATCH_CANDIDATES)}:{sources_hash()}")
-    if use_cache and candidates is None:
+           f"{_candidates_hash(cands)}:{sources_hash()}")
+    if use_cache:
         hit = _load_cache().get(key)
         if hit:
             batch.set_tiling(**hit["tiling"])
             return hit
     trials = []
-    for cand in candidates or DEFAULT_BATCH_CANDIDATES:
+    for cand in cands:
         batch.set_tiling(**cand)
         per = cand["depth"] * 3
         n = max(per, (steps // per) * per)
@@ -138,8 +139,9 @@ def tune_batch(batch, params: list[dict], candidates=None, steps: int = 24,
 def tune_sim(sim, candidates=None, steps: int = 48, use_cache: bool = True) -> dict:
     """Tunes depth and band of a standalone simulation (advances it)."""
     sig = json.dumps([sim.width, sim.height, sim.rules, sim.force_rate > 0, sim.has_mask, sim.walls])
-    key = f"sim:{_gpu_name()}:{sig}:{_candidates_hash(DEFAULT_SIM_CANDIDATES)}:{sources_hash()}"
-    if use_cache and candidates is None:
+    cands = candidates or DEFAULT_SIM_CANDIDATES
+    key = f"sim:{_gpu_name()}:{sig}:{_candidates_hash(cands)}:{sources_hash()}"
+    if use_cache:
         hit = _load_cache().get(key)
         if hit:
             sim.depth = hit["tiling"]["depth"]
@@ -147,7 +149,7 @@ def tune_sim(sim, candidates=None, steps: int = 48, use_cache: bool = True) -> d
             return hit
     stream = torch.cuda.current_stream()
     trials = []
-    for cand in candidates or DEFAULT_SIM_CANDIDATES:
+    for cand in cands:
         try:
             sim.depth = cand["depth"]
             sim.set_band(min(cand["band"], sim.height))
