@@ -144,8 +144,9 @@ int fhp_create(const fhp_params *p, void *dev_ws, size_t ws_bytes, void *hip_str
 
 /* Temporal-block depth k (1..FHP_MAX_DEPTH): fhp_step runs k steps per pass over
  * HBM (the last pass of a call may be shorter).  0 selects the library's default
- * for this lattice: FHP_MAX_DEPTH, or 3 where the lattice is too small to give
- * every SIMD of the device two waves (as for 4096 x 4096 on 256 compute units).
+ * for this lattice: 3 where the lattice is too small to give every SIMD of the
+ * device two waves (as for 4096 x 4096 on 256 compute units), 4 where the
+ * default band (fhp_get_band) is 8 rows or fewer, FHP_MAX_DEPTH otherwise.
  * k > 1 needs width <= 32768.
  * FHP_RULES_FHP3 lattices run passes of at most 3 steps whatever k.  Results
  * do not depend on k. */

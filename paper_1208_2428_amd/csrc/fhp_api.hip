@@ -162,18 +162,21 @@ uint32_t default_band(uint32_t H, uint32_t wd, uint32_t simds) {
     return band_rule(H, wd, simds, &one_wave);
 }
 
-// Default depth: FHP_MAX_DEPTH, except on lattices too small to give every
+// Default depth from the default band: 3 on lattices too small to give every
 // SIMD two waves, where a pass is bound by the latency of its level chain
-// rather than by memory and 3 steps per pass (25% less halo work than 5 at
-// 4-row bands) are faster: 4096^2 channel flow at K = 2..5 measured 4.87e12,
-// 4.95e12, 4.72e12 and 4.56e12 node-updates/s, 2048^2 at 2-row bands 1.45e12,
-// 1.49e12, 1.40e12 and 1.29e12.  Rows wider than the blocked kernel takes run
-// single steps.
+// rather than by memory (25% less halo work per step than 5 at 4-row bands):
+// 4096^2 channel flow at K = 2..5 measured 4.87e12, 4.95e12, 4.72e12 and
+// 4.56e12 node-updates/s, 2048^2 at 2-row bands 1.45e12, 1.49e12, 1.40e12 and
+// 1.29e12.  4 where the bands are 8 rows or shorter (8192^2 at 8-row bands
+// 8.26e12 at K = 4, 8.04e12 at 5; 8192 x 4096 at 4-row bands 5.81e12 and
+// 5.52e12), FHP_MAX_DEPTH otherwise (16384^2 at 32-row bands: 1.07e13 at 5,
+// 0.99e13 at 4).  Rows wider than the blocked kernel takes run single steps.
 uint32_t default_depth(uint32_t H, uint32_t wd, uint32_t simds) {
     if (wd > kMaxBlockedWords) return 1;
     bool one_wave;
-    band_rule(H, wd, simds, &one_wave);
-    return one_wave ? 3 : FHP_MAX_DEPTH;
+    const uint32_t T = band_rule(H, wd, simds, &one_wave);
+    if (one_wave) return 3;
+    return T <= 8 ? 4 : FHP_MAX_DEPTH;
 }
 
 Dyn dyn_for(const fhp_params* p) {

@@ -160,9 +160,9 @@ def test_band_runs_per_xcd(W, H, band, K):
 
 
 def test_default_depth_and_band():
-    """The default depth is 5 steps per pass, or 3 on lattices too small to
-    give every SIMD two waves; the default band is the largest even height up
-    to 32 rows that gives every SIMD two waves (else one)."""
+    """The default band is the largest even height up to 32 rows that gives
+    every SIMD two waves (else one); the default depth is 3 on lattices too
+    small to give every SIMD two waves, 4 at bands of 8 rows or fewer, else 5."""
     import torch
     simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
 
@@ -178,9 +178,10 @@ def test_default_depth_and_band():
         one = T < 4
         if one:
             T = max(largest(simds), 2)
-        return (3 if one else 5), min(T, H)
+        return (3 if one else 4 if T <= 8 else 5), min(T, H)
 
-    for W, H in [(4096, 4096), (2048, 2048), (8192, 8192), (16384, 16384), (4096, 65536), (256, 256)]:
+    for W, H in [(4096, 4096), (2048, 2048), (8192, 8192), (8192, 4096), (16384, 16384),
+                 (4096, 65536), (256, 256)]:
         s = Sim(W, H, seed=1)
         assert (s.depth, s.band) == expected(W, H), (W, H)
         s.depth = 2
