@@ -22,7 +22,13 @@
 // synchronises, and each thread reads its two neighbours' halves (wrapping at
 // the row ends).  Every shift is then two funnel shifts (v_alignbit) with no
 // bit packing.  Two LDS slots alternate so that one barrier per exchange
-// suffices.
+// suffices.  Rows of exactly 64 words (ONE_WAVE) are one wave per band, and
+// the halves move between neighbouring lanes by DPP rotations instead, with
+// no LDS and no barrier.
+//
+// Loads.  Rows are loaded two iterations ahead of their use.  Launches of at
+// most one wave per SIMD (PRELOAD), where no other wave hides a load's
+// latency, load the 2K + 2 rows of the pipeline fill at once.
 //
 // Row parity.  Odd rows are shifted by +1/2, so which planes shift depends on
 // the parity of the destination row.  With y0 and H even it equals the
