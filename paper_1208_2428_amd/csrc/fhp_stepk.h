@@ -22,9 +22,9 @@
 // synchronises, and each thread reads its two neighbours' halves (wrapping at
 // the row ends).  Every shift is then two funnel shifts (v_alignbit) with no
 // bit packing.  Two LDS slots alternate so that one barrier per exchange
-// suffices.  Rows of exactly 64 words (ONE_WAVE) are one wave per band, and
-// the halves move between neighbouring lanes by DPP rotations instead, with
-// no LDS and no barrier.
+// suffices.  Rows of 64 words, or of a power of two fewer repeated across
+// the 64 lanes (ONE_WAVE), are one wave per band, and the halves move between
+// neighbouring lanes by DPP rotations instead, with no LDS and no barrier.
 //
 // Loads.  Rows are loaded two iterations ahead of their use.  Launches of at
 // most one wave per SIMD (PRELOAD), where no other wave hides a load's
@@ -71,8 +71,11 @@ __device__ inline uint32_t band_of(uint32_t b, uint32_t nb, uint32_t runs) {
 
 constexpr size_t kStepkLdsBytes = 2 * 4 * kMaxBlockedWords * sizeof(uint32_t);
 
-// ONE_WAVE: rows of exactly 64 words, one wave per band; the carries move
-// between lanes by DPP (gather_wave) instead of through LDS.  PRELOAD: the
+// ONE_WAVE: rows of wd words, wd a power of two up to 64, one wave per band:
+// lane l holds word l mod wd, so that the row repeats 64 / wd times across
+// the wave and a rotation of the whole wave by one lane brings every lane its
+// periodic neighbour; the carries move by DPP (gather_wave) instead of through
+// LDS.  Only the first copy stores.  PRELOAD: the
 // 2K + 2 rows of the pipeline fill are loaded at once, for launches of at most
 // one wave per SIMD (see launch_stepk).
 template <int K, bool FORCE, bool MASK, int RULES, bool WIDE, bool ONE_WAVE = false,
@@ -83,7 +86,7 @@ __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
     extern __shared__ uint32_t xch[];  // 2 slots x 4 halves x kMaxBlockedWords entries
     const uint32_t lane = threadIdx.x;
     const bool valid = lane < a.wd;
-    const uint32_t w = valid ? lane : 0;
+    const uint32_t w = ONE_WAVE ? (lane & (a.wd - 1)) : (valid ? lane : 0);
     const uint32_t wl = w ? w - 1 : a.wd - 1;
     const uint32_t wr = (w + 1 == a.wd) ? 0 : w + 1;
     const uint32_t H = a.H;
@@ -297,7 +300,7 @@ hipError_t launch_k(const uint64_t* in, uint64_t* out, const Lattice& L, const S
     const uint32_t nt = (L.wd + 63) / 64 * 64;
     const uint32_t bands = (L.H + a.T - 1) / a.T;
     if constexpr (ONE_WAVE) {
-        if (L.wd != 64) return hipErrorInvalidValue;
+        if (L.wd == 0 || 64 % L.wd != 0) return hipErrorInvalidValue;
         hipLaunchKernelGGL((k_stepk<K, FORCE, MASK, RULES, WIDE, true, PRELOAD>), dim3(bands),
                            dim3(64), 0, st, in, out, L.S, a);
     } else {
@@ -329,7 +332,8 @@ hipError_t launch_k2(const uint64_t* in, uint64_t* out, const Lattice& L, const 
 }
 
 // Launches the pass of depth K for buffers of the given width class
-// (OW: the one-wave kernel for rows of 64 words; PL: the preloaded fill).
+// (OW: the one-wave kernel for rows of a power of two words up to 64; PL: the
+// preloaded fill).
 template <bool WIDE, bool OW = false, bool PL = false>
 hipError_t launch_depth(uint32_t K, const uint64_t* in, uint64_t* out, const Lattice& L, const StepkArgs& a,
                         uint32_t rules, hipStream_t st) {
@@ -349,7 +353,8 @@ hipError_t launch_depth(uint32_t K, const uint64_t* in, uint64_t* out, const Lat
 // own translation unit so that the two halves compile in parallel).
 hipError_t launch_stepk_wide(uint32_t K, const uint64_t* in, uint64_t* out, const Lattice& L,
                              const StepkArgs& a, uint32_t rules, hipStream_t st);
-// The pass for rows of exactly 64 words, one wave per band (fhp_stepk_wave.hip).
+// The pass for rows of a power of two words up to 64, one wave per band
+// (fhp_stepk_wave.hip).
 hipError_t launch_stepk_wave(uint32_t K, const uint64_t* in, uint64_t* out, const Lattice& L,
                              const StepkArgs& a, uint32_t rules, hipStream_t st);
 // The passes with the preloaded pipeline fill, for launches of at most one

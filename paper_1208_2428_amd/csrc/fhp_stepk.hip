@@ -32,8 +32,12 @@ hipError_t launch_stepk(uint32_t K, const uint64_t* in, uint64_t* out, const Lat
     // (4-row bands), on 2048^2 +5%.  With two waves per SIMD the other wave
     // hides it and the preload costs 1-5% (16384^2, 8192^2, 4096 x 65536).
     const uint64_t waves = (uint64_t)((L.H + a.T - 1) / a.T) * ((L.wd + 63) / 64);
-    if (waves <= simds) return launch_stepk_preload(K, in, out, L, a, D.rules, L.wd == 64, st);
-    if (L.wd == 64) return launch_stepk_wave(K, in, out, L, a, D.rules, st);
+    // Rows of a power of two words up to 64 run one wave per band with DPP
+    // carries (the row repeated across the wave); other widths exchange
+    // carries through LDS.
+    const bool one_wave = 64 % L.wd == 0;
+    if (waves <= simds) return launch_stepk_preload(K, in, out, L, a, D.rules, one_wave, st);
+    if (one_wave) return launch_stepk_wave(K, in, out, L, a, D.rules, st);
     return launch_depth<false>(K, in, out, L, a, D.rules, st);
 }
 

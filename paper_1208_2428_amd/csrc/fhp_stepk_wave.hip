@@ -1,6 +1,7 @@
 // fhp_stepk_wave.hip -- the temporally blocked pass (kernel in fhp_stepk.h)
-// for rows of exactly 64 words: one wave per band, carries between lanes by
-// DPP (its own translation unit so that it compiles in parallel).
+// for rows of a power of two words up to 64: one wave per band, carries
+// between lanes by DPP (its own translation unit so that it compiles in
+// parallel).
 #include "fhp_stepk.h"
 
 namespace fhp {

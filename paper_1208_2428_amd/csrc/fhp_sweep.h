@@ -172,11 +172,11 @@ __device__ __forceinline__ void gather(const uint32_t* xch, uint32_t& slot, uint
     slot ^= 1;
 }
 
-// Rows held by a single wave (64 words, lane = word): the neighbour halves come
-// from the adjacent lanes through DPP wave rotations, with no LDS and no
-// barrier.  wave_ror:1 hands each lane the value of the lane below it (lane 0
-// gets lane 63's: the periodic wrap of a 64-word row), wave_rol:1 the value
-// of the lane above it.
+// Rows held by a single wave (64 words, lane = word, or fewer words repeated
+// across the wave): the neighbour halves come from the adjacent lanes through
+// DPP wave rotations, with no LDS and no barrier.  wave_ror:1 hands each lane
+// the value of the lane below it (lane 0 gets lane 63's: the periodic wrap of
+// the row), wave_rol:1 the value of the lane above it.
 __device__ __forceinline__ uint32_t from_left_lane(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x13C, 0xf, 0xf, false);
 }

@@ -217,3 +217,29 @@ def test_preloaded_and_streamed_fill(W, band, K):
             t += n
             np.testing.assert_array_equal(s.get_state(), ref, err_msg=f"H={H} t={t}")
         s.close()
+
+
+@pytest.mark.parametrize("W", [64, 128, 256, 512, 1024, 2048])
+@pytest.mark.parametrize("K", [2, 3, 5])
+@pytest.mark.parametrize("rules", [0, 2])
+def test_repeated_row_one_wave(W, K, rules):
+    """Rows of 1 to 32 words run the one-wave pass with the row repeated
+    across the wave's 64 lanes (a whole-wave rotation then brings every lane
+    its periodic neighbour; only the first copy stores): every pass equals the
+    oracle, with walls, obstacles, particles on solid nodes and forcing."""
+    H = 46
+    say("repeated row", W, K, rules)
+    rng = np.random.default_rng(W + 10 * K + rules)
+    st = make_state(rng, W, H, "solid-particles")
+    st[0] |= 0x80
+    st[-1] |= 0x80
+    f = 1.0 / 70
+    s = Sim(W, H, seed=19, force_rate=f, walls=True, depth=K, band=6, rules=rules)
+    s.set_state(st, t=4)
+    ref, t = st.copy(), 4
+    for n in (K, 2 * K + 1, 3):
+        s.step(n)
+        ref, _ = oracle.run(ref, t, n, 19, f, threads=THREADS, rules=rules)
+        t += n
+        np.testing.assert_array_equal(s.get_state(), ref, err_msg=f"t={t}")
+    s.close()
