@@ -1,7 +1,7 @@
-"""Randomised GPU vs oracle parity: 160 seeded single-lattice configurations
+"""Randomised GPU vs oracle parity: 480 seeded single-lattice configurations
 drawn over widths, heights, depths, band heights, walls, obstacles (solid
 nodes holding particles included), forcing rates, chirality modes, rule sets
-and step sequences; 24 seeded batches with random tilings; 12 seeded job
+and step sequences; 64 seeded batches with random tilings; 32 seeded job
 streams through pools.  Every result is compared bit for bit with the oracle.
 The draws are fixed by the seeds, so a failure names a reproducible case."""
 import numpy as np
@@ -36,7 +36,7 @@ def draw(case: int) -> dict:
     )
 
 
-@pytest.mark.parametrize("case", range(160))
+@pytest.mark.parametrize("case", range(480))
 def test_random_configuration(case):
     c = draw(case)
     print("random case", case, c, flush=True)
@@ -84,7 +84,7 @@ def draw_batch(case: int) -> dict:
     )
 
 
-@pytest.mark.parametrize("case", range(24))
+@pytest.mark.parametrize("case", range(64))
 def test_random_batch(case):
     """Seeded batches of 2-6 uneven lattices of one rule set with random
     tiling (depth, band height, workgroup size, passes per launch, graph
@@ -109,7 +109,7 @@ def test_random_batch(case):
     b.close()
 
 
-@pytest.mark.parametrize("case", range(12))
+@pytest.mark.parametrize("case", range(32))
 def test_random_pool(case):
     """Seeded job streams through a pool: jobs of random size, step count and
     physics (one rule set per pool) admitted between ticks of random length,
