@@ -75,9 +75,9 @@ constexpr size_t kStepkLdsBytes = 2 * 4 * kMaxBlockedWords * sizeof(uint32_t);
 // lane l holds word l mod wd, so that the row repeats 64 / wd times across
 // the wave and a rotation of the whole wave by one lane brings every lane its
 // periodic neighbour; the carries move by DPP (gather_wave) instead of through
-// LDS.  Only the first copy stores.  PRELOAD: the
-// 2K + 2 rows of the pipeline fill are loaded at once, for launches of at most
-// one wave per SIMD (see launch_stepk).
+// LDS.  Only the first copy stores.
+// PRELOAD: the 2K + 2 rows of the pipeline fill are loaded at once, for
+// launches of at most one wave per SIMD (see launch_stepk).
 template <int K, bool FORCE, bool MASK, int RULES, bool WIDE, bool ONE_WAVE = false,
           bool PRELOAD = false>
 __global__ void __launch_bounds__(512) k_stepk(const uint64_t* __restrict__ in,
