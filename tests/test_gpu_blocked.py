@@ -243,3 +243,26 @@ def test_repeated_row_one_wave(W, K, rules):
         t += n
         np.testing.assert_array_equal(s.get_state(), ref, err_msg=f"t={t}")
     s.close()
+
+
+@pytest.mark.parametrize("W", [32768, 32704, 4160, 128 * 64 + 64])
+@pytest.mark.parametrize("K", [2, 5])
+def test_widest_rows(W, K):
+    """The widest rows the blocked pass takes (512 words: eight waves per band
+    exchanging carries through LDS), one word short of it (the last lane of the
+    workgroup idle), and widths just past a wave (65 and 129 words: most lanes
+    of the last wave idle): every pass equals the oracle."""
+    H = 14
+    say("widest", W, K)
+    rng = np.random.default_rng(W + K)
+    st = make_state(rng, W, H, "mask+force")
+    f = 1.0 / 70
+    s = Sim(W, H, seed=23, force_rate=f, depth=K)
+    s.set_state(st, t=7)
+    ref, t = st.copy(), 7
+    for n in (K, 2 * K + 1):
+        s.step(n)
+        ref, _ = oracle.run(ref, t, n, 23, f, threads=THREADS)
+        t += n
+        np.testing.assert_array_equal(s.get_state(), ref, err_msg=f"t={t}")
+    s.close()
