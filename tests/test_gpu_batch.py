@@ -101,3 +101,26 @@ def test_ensemble_sample_matches_oracle():
     b.sync()
     for i, kw in enumerate(params):
         assert b[i].digest() == oracle.digest(oracle_state(kw, 10)), i
+
+
+@pytest.mark.parametrize("depth,band", [(2, 0), (5, 8)])
+def test_batch_with_widest_member(depth, band):
+    """A member of the widest rows a batch takes (512 words: the workgroup is
+    raised to 512 threads, eight waves per band) beside narrow ones: every
+    member equals its oracle run."""
+    params = [
+        dict(width=32768, height=8, seed=31, fill=0.3, force_rate=1e-2, walls=True),
+        dict(width=4160, height=10, seed=32, fill=0.25),
+        dict(width=128, height=12, seed=33, fill=0.4, force_rate=5e-3),
+    ]
+    say("widest member", depth, band)
+    b = Batch(params, depth=depth, band=band)
+    steps = 0
+    for n in (depth, 2 * depth + 1):
+        b.step(n)
+        steps += n
+        b.sync()
+        for i, kw in enumerate(params):
+            np.testing.assert_array_equal(b[i].get_state(), oracle_state(kw, steps),
+                                          err_msg=f"member {i} after {steps} steps")
+    b.close()
