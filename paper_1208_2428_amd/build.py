@@ -20,6 +20,13 @@ HIPCC_FLAGS = [
 ]
 
 
+# Per-source extra flags.  The depth-5 pass of wide lattices is scheduled for
+# instruction-level parallelism (see fhp_stepk_k5.hip).
+FILE_FLAGS = {
+    "fhp_stepk_k5.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+}
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
@@ -43,7 +50,8 @@ def build(verbose: bool = False) -> str:
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + "." + tag + ".o")
         objs.append(obj)
-        cmds.append([hipcc, *HIPCC_FLAGS, "-c", *inc, "-o", obj, src])
+        extra = FILE_FLAGS.get(os.path.basename(src), [])
+        cmds.append([hipcc, *HIPCC_FLAGS, *extra, "-c", *inc, "-o", obj, src])
     jobs = max(1, min(len(cmds), os.cpu_count() or 1, 8))
     try:
         with concurrent.futures.ThreadPoolExecutor(jobs) as ex:

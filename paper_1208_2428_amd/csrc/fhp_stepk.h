@@ -333,8 +333,9 @@ hipError_t launch_k2(const uint64_t* in, uint64_t* out, const Lattice& L, const 
 
 // Launches the pass of depth K for buffers of the given width class
 // (OW: the one-wave kernel for rows of a power of two words up to 64; PL: the
-// preloaded fill).
-template <bool WIDE, bool OW = false, bool PL = false>
+// preloaded fill).  KMAX: the deepest pass this instantiation launches (deeper
+// ones are left to another translation unit).
+template <bool WIDE, bool OW = false, bool PL = false, int KMAX = 5>
 hipError_t launch_depth(uint32_t K, const uint64_t* in, uint64_t* out, const Lattice& L, const StepkArgs& a,
                         uint32_t rules, hipStream_t st) {
     switch (K) {
@@ -342,7 +343,9 @@ hipError_t launch_depth(uint32_t K, const uint64_t* in, uint64_t* out, const Lat
         case 2: return launch_k2<WIDE, 2, OW, PL>(in, out, L, a, rules, st);
         case 3: return launch_k2<WIDE, 3, OW, PL>(in, out, L, a, rules, st);
         case 4: return launch_k2<WIDE, 4, OW, PL>(in, out, L, a, rules, st);
-        case 5: return launch_k2<WIDE, 5, OW, PL>(in, out, L, a, rules, st);
+        case 5:
+            if constexpr (KMAX >= 5) return launch_k2<WIDE, 5, OW, PL>(in, out, L, a, rules, st);
+            return hipErrorInvalidValue;
         default: return hipErrorInvalidValue;
     }
 }
@@ -353,6 +356,10 @@ hipError_t launch_depth(uint32_t K, const uint64_t* in, uint64_t* out, const Lat
 // own translation unit so that the two halves compile in parallel).
 hipError_t launch_stepk_wide(uint32_t K, const uint64_t* in, uint64_t* out, const Lattice& L,
                              const StepkArgs& a, uint32_t rules, hipStream_t st);
+// The depth-5 pass with LDS carries and the streamed fill, for state buffers
+// below 4 GiB (fhp_stepk_k5.hip, compiled with its own instruction schedule).
+hipError_t launch_stepk_k5(const uint64_t* in, uint64_t* out, const Lattice& L, const StepkArgs& a,
+                           uint32_t rules, hipStream_t st);
 // The pass for rows of a power of two words up to 64, one wave per band
 // (fhp_stepk_wave.hip).
 hipError_t launch_stepk_wave(uint32_t K, const uint64_t* in, uint64_t* out, const Lattice& L,

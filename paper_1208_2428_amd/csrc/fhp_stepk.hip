@@ -38,7 +38,8 @@ hipError_t launch_stepk(uint32_t K, const uint64_t* in, uint64_t* out, const Lat
     const bool one_wave = 64 % L.wd == 0;
     if (waves <= simds) return launch_stepk_preload(K, in, out, L, a, D.rules, one_wave, st);
     if (one_wave) return launch_stepk_wave(K, in, out, L, a, D.rules, st);
-    return launch_depth<false>(K, in, out, L, a, D.rules, st);
+    if (K == 5) return launch_stepk_k5(in, out, L, a, D.rules, st);
+    return launch_depth<false, false, false, 4>(K, in, out, L, a, D.rules, st);
 }
 
 }  // namespace fhp

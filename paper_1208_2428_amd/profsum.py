@@ -18,16 +18,20 @@ from collections import defaultdict
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
-# Sources of the blocked single-lattice kernel: the traffic recorded under
-# profiles/ applies only while they are unchanged.
-KERNEL_SOURCES = ["csrc/fhp_stepk.h", "csrc/fhp_stepk.hip", "csrc/fhp_sweep.h", "csrc/fhp_device.h"]
+# Sources of the blocked single-lattice kernel, and the extra compiler flags of
+# the depth-5 pass: the traffic recorded under profiles/ applies only while
+# they are unchanged.
+KERNEL_SOURCES = ["csrc/fhp_stepk.h", "csrc/fhp_stepk.hip", "csrc/fhp_stepk_k5.hip",
+                  "csrc/fhp_sweep.h", "csrc/fhp_device.h"]
 
 
 def kernel_source_hash() -> str:
+    from . import build
     h = hashlib.sha1()
     for rel in KERNEL_SOURCES:
         with open(os.path.join(PKG, rel), "rb") as fh:
             h.update(fh.read())
+    h.update(repr(build.FILE_FLAGS.get("fhp_stepk_k5.hip", [])).encode())
     return h.hexdigest()[:12]
 
 
