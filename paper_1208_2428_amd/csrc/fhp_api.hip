@@ -122,14 +122,6 @@ Layout layout_for(uint32_t W, uint32_t H) {
     return l;
 }
 
-// Default temporal-block depth where the blocked kernel applies (full-row
-// workgroups, at most kMaxBlockedWords words per row): the deepest whose
-// register queue fits without spilling.  On the 16384^2 porous lattice every
-// shallower depth runs at the copy bandwidth of HBM (halo rows included);
-// depth 5 moves 18% fewer bytes per step than depth 4 for 3% more halo work,
-// measured 3-6% faster, and is near both that bandwidth and the VALU issue
-// limit.
-
 // Default band height of the blocked kernel, from occupancy: the largest even
 // height up to 32 rows whose bands give every SIMD two waves (a band's
 // workgroup holds ceil(wd / 64) waves); if that takes bands of 2 rows, the
@@ -169,8 +161,10 @@ uint32_t default_band(uint32_t H, uint32_t wd, uint32_t simds) {
 // 4.56e12 node-updates/s, 2048^2 at 2-row bands 1.45e12, 1.49e12, 1.40e12 and
 // 1.29e12.  4 where the bands are 8 rows or shorter (8192^2 at 8-row bands
 // 8.26e12 at K = 4, 8.04e12 at 5; 8192 x 4096 at 4-row bands 5.81e12 and
-// 5.52e12), FHP_MAX_DEPTH otherwise (16384^2 at 32-row bands: 1.07e13 at 5,
-// 0.99e13 at 4).  Rows wider than the blocked kernel takes run single steps.
+// 5.52e12), FHP_MAX_DEPTH otherwise: the deepest pass whose register queue
+// fits without spilling, which moves 18% fewer bytes per step than depth 4
+// for 3% more halo work (16384^2 at 32-row bands: 1.07e13 at 5, 0.99e13 at
+// 4).  Rows wider than the blocked kernel takes run single steps.
 uint32_t default_depth(uint32_t H, uint32_t wd, uint32_t simds) {
     if (wd > kMaxBlockedWords) return 1;
     bool one_wave;
