@@ -20,6 +20,8 @@ from collections import Counter
 
 import torch
 
+from ._binding import FhpError
+
 DEFAULT_BATCH_CANDIDATES = [
     dict(depth=k, band=b, group_threads=nt, passes_per_launch=ppl)
     for k in (1, 2, 3, 4, 5) for b in (8, 16, 32, 64) for nt in (64, 256) for ppl in (1, 0)
@@ -150,10 +152,10 @@ def tune_sim(sim, candidates=None, steps: int = 48, use_cache: bool = True) -> d
     stream = torch.cuda.current_stream()
     trials = []
     for cand in cands:
-        try:
+        try:  # a depth this lattice does not take (width above 32768) is skipped
             sim.depth = cand["depth"]
             sim.set_band(min(cand["band"], sim.height))
-        except Exception:
+        except FhpError:
             continue
         n = max(12, (steps // 12) * 12)
         trials.append((cand, time_steps(sim.step, stream, n, 1)))
