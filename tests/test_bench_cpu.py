@@ -43,3 +43,16 @@ def test_recorded_profile_fields():
     assert traffic and traffic > 4.7e8  # at least the algorithmic bytes of a 16384^2 pass
     assert depth == 5 and src and len(src) == 12
     assert profsum.recorded_value(md, "valu_insts_per_launch") > 0
+
+
+def test_build_flags_and_kernel_sources_name_existing_files():
+    """Per-source compiler flags and the sources whose hash gates the recorded
+    traffic must name files that exist (a renamed source would otherwise drop
+    its flags, or leave the recorded traffic gated on nothing)."""
+    import os
+    from paper_1208_2428_amd import build
+    names = {os.path.basename(p) for p in build.sources()}
+    assert set(build.FILE_FLAGS) <= names
+    for rel in profsum.KERNEL_SOURCES:
+        assert os.path.exists(os.path.join(profsum.PKG, rel)), rel
+    assert "csrc/fhp_stepk_k5.hip" in profsum.KERNEL_SOURCES
