@@ -199,9 +199,10 @@ void fhp_destroy(fhp_sim *s);
  * two neighbouring bands' previous pass (per-band counters on the device).
  * Each member's results are identical to those of a standalone simulation with
  * the same parameters (Sec. 2 model; the same readings as above).
- * Members need width <= 32768 and height >= FHP_BATCH_MIN_HEIGHT, and all
- * members share one rule set (FHP_RULES_FHP3 batches run passes of at most 3
- * steps).
+ * Members need width <= 32768, height >= FHP_BATCH_MIN_HEIGHT and seven
+ * planes of at most 4 GiB (width x height below about 4.9e9 nodes; larger
+ * lattices run as single simulations), and all members share one rule set
+ * (FHP_RULES_FHP3 batches run passes of at most 3 steps).
  * ------------------------------------------------------------------------- */
 typedef struct fhp_batch fhp_batch;
 
@@ -251,7 +252,8 @@ void fhp_batch_destroy(fhp_batch *b);
  * jobs (one batch-kernel launch per pass over all of them, each job clipped to
  * its remaining steps; the last steps that do not fill a pass run on the
  * single-lattice kernels).  A job's result does not depend on the other jobs
- * or on when it was admitted.  Members need width <= 32768 and height >= 8.
+ * or on when it was admitted.  Members need width <= 32768, height >= 8 and
+ * seven planes of at most 4 GiB.
  * ------------------------------------------------------------------------- */
 typedef struct fhp_pool fhp_pool;
 

@@ -95,6 +95,12 @@ def test_batch_and_pool_argument_checks(lib):
     planes = (128 * 64 + 256 * 32) // 8
     assert n.value >= 15 * planes
     assert lib.fhp_batch_workspace_bytes(arr, 0, ctypes.byref(n)) == B.E_INVAL
+    # a member whose seven planes exceed 4 GiB (32768 x 149800: 7 x 613.6 MB):
+    # batches address a member's planes through one 32-bit-offset resource
+    arr[1], _ = B.make_params(32768, 149800)
+    assert lib.fhp_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == B.E_INVAL
+    arr[1], _ = B.make_params(32768, 149700)  # 7 x 613.2 MB: fits
+    assert lib.fhp_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == B.OK
     h = ctypes.c_void_p()
     assert lib.fhp_batch_create(arr, 2, None, n.value, None, ctypes.byref(h)) == B.E_INVAL
     assert lib.fhp_pool_workspace_bytes(0, 16, 1 << 20, ctypes.byref(n)) == B.E_INVAL
