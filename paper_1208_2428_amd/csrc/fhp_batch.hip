@@ -173,15 +173,16 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
         const uint32_t wl = valid ? first + (w ? w - 1 : wd - 1) : lane;
         const uint32_t wr = valid ? first + ((w + 1 == wd) ? 0 : w + 1) : lane;
         const uint32_t cur = (uni(M->cur) + p) & 1;
-        // Planes either through buffer resources, one per state buffer (a
-        // member's seven planes lie within 4 GiB, checked when it is added:
+        // Planes are read through buffer resources, one per state buffer (a
+        // member's seven planes lie within 4 GiB, checked when it is added):
         // the row offset in a vector register, the plane offset in a scalar
         // one, no 64-bit address arithmetic; a member without obstacles gets
-        // an empty range for S, whose loads return 0 without touching memory),
-        // or through global pointers.  Measured on the 512-lattice ensemble
-        // (no forcing) the resources ran 1.7% faster; on the served stream
-        // (forcing) 1.1% slower, so the forcing variants keep the pointers.
-        constexpr bool kRsrc = !FORCE;
+        // an empty range for S, whose loads return 0 without touching memory.
+        // Output rows are stored the same way without forcing (the 512-lattice
+        // ensemble ran 1.5% faster than with 64-bit global pointers); with
+        // forcing through global pointers (the served stream ran 1.1% slower
+        // with resource stores, 0.25% faster with resource loads).
+        constexpr bool kRsrcStore = !FORCE;
         const uint64_t ps = uni(M->ps);
         const uint64_t in_addr = uni((uint64_t)M->buf[cur]);
         const uint64_t out_addr = uni((uint64_t)M->buf[cur ^ 1]);
@@ -189,13 +190,11 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
         const Planes<false> pin((const uint64_t*)in_addr, ps, 0);
         const Planes<false> pout((const uint64_t*)out_addr, ps, 0);
         const __amdgpu_buffer_rsrc_t rs = region_rsrc((const void*)s_addr, s_addr ? (uint32_t)(ps * 8) : 0u);
-        // global (not generic) pointers: generic accesses would also count
+        // global (not generic) pointer: generic accesses would also count
         // against the LDS wait of every carry exchange
-        const GlobalU64* in = (const GlobalU64*)in_addr;
         GlobalU64* out = (GlobalU64*)out_addr;
-        const GlobalU64* S = (const GlobalU64*)s_addr;
         auto store_plane = [&](int c, uint32_t boff, uint64_t v) __attribute__((always_inline)) {
-            if constexpr (kRsrc)
+            if constexpr (kRsrcStore)
                 pout.store(c, boff, v);
             else
                 __builtin_nontemporal_store(v, (GlobalU64*)((GlobalChar*)(out + c * ps) + boff));
@@ -227,16 +226,9 @@ __global__ void __launch_bounds__(512) k_batch(BatchHeader* __restrict__ hdr,
         };
         auto load = [&](int d, Row& x) __attribute__((always_inline)) {
             const uint32_t boff = row_off(d) * 8u;
-            if constexpr (kRsrc) {
 #pragma unroll
-                for (int c = 0; c < 7; c++) x.p[c] = pin.load(c, boff);
-                if (MASK) x.s = buf_load64(rs, boff, 0);
-            } else {
-#pragma unroll
-                for (int c = 0; c < 7; c++)
-                    x.p[c] = *(const GlobalU64*)((const GlobalChar*)(in + c * ps) + boff);
-                if (MASK) x.s = S ? *(const GlobalU64*)((const GlobalChar*)S + boff) : 0ull;
-            }
+            for (int c = 0; c < 7; c++) x.p[c] = pin.load(c, boff);
+            if (MASK) x.s = buf_load64(rs, boff, 0);
         };
 
         uint64_t a3[K + 1], a4[K + 1], bp[K + 1][7], bs[K + 1];
